@@ -1,0 +1,194 @@
+/*
+ * gw.h - C ABI of the MI355X (gfx950) static polarizability library.
+ *
+ * The library builds the static polarizability of a plane-wave GW
+ * calculation in real space (paper: "Scalable GW software for quasiparticle
+ * properties using OpenAtom", Sec. 4.1 and Sec. 5.1):
+ *
+ *   f_vc(r)   = conj(u_v(r)) u_c(r) sqrt(p / (E_c - E_v))              Eq.(fdef)
+ *   P(r,r')   = - sum_vc conj(f_vc(r)) f_vc(r')                        outer product below Eq.(fdef), N_k = 1
+ *   P^(g,r')  = sum_r  exp(-i G_g.r)   P(r,r')                         first transform, Sec. 4.1
+ *   P~(g,g')  = sum_r' P^(g,r') exp(+i G_g'.r')                        second transform, Sec. 4.1
+ *   eps(g,g') = delta - sqrt(V(q+g)) P~(g,g') sqrt(V(q+g'))            Sec. 5.1
+ *   V(q+g)    = 4 pi / (Omega |q+g|^2)                                 Sec. 5.1, Hartree atomic units
+ *   eps^-1                                                             Sec. 5.1 (here: FP64 Cholesky)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array arguments are DEVICE pointers unless marked (host).  Arrays are
+ *   row-major.  Complex numbers are interleaved {re, im}.
+ * - Orbitals: psi[n][nr], grid-normalised (sum_r |psi|^2 = 1), with grid index
+ *   r = (i1*n2 + i2)*n3 + i3.
+ * - Energies are float64 in Hartree.  Every E_c - E_v must be > 0.
+ * - The G-sphere is an ordered host list of Miller triples g_miller[ng][3]
+ *   (int32) with |m_d| < n_d/2 and no duplicates; outputs indexed by g follow
+ *   that order.  q is in crystal units; the cell is cubic with side a_bohr.
+ * - Where |q+G| < 1e-10 * 2pi/a, sqrt(V) is taken as 0 and eps(g,g) is set to
+ *   the caller's `head` value (the wings become 0).
+ * - Ownership: the caller owns every buffer it passes and the library never
+ *   frees them.  The context owns its device workspace, bounded by the cap
+ *   given at creation.  Host arrays are read during the call only.
+ * - Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *   asynchronous on that stream unless stated otherwise.
+ * - Errors: every call returns a gw_status; no exception crosses the ABI.  All
+ *   argument checks run on the host before any device work is queued; on a
+ *   failed check nothing is launched and gw_last_error(ctx) describes it.
+ *   A context is not thread-safe: use one per host thread.
+ * - Dry-run contexts (gw_create with hip_device = -1) run every argument
+ *   check and return GW_OK without touching any device; they exist so that
+ *   callers can validate arguments on machines without a GPU.
+ */
+#ifndef GW_H
+#define GW_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gw_ctx gw_ctx;
+typedef struct { float re, im; } gw_c32;
+typedef struct { double re, im; } gw_c64;
+typedef struct { int n1, n2, n3; double a_bohr; } gw_grid;
+
+enum gw_status {
+  GW_OK = 0,
+  GW_E_INVAL = 1,        /* bad argument (shape, pointer, energy order, sphere) */
+  GW_E_NOMEM = 2,        /* the workspace cap or the device memory is exceeded */
+  GW_E_HIP = 3,          /* a HIP runtime call or kernel launch failed */
+  GW_E_NOTPD = 4,        /* eps is not positive definite (pivot index in gw_last_error) */
+  GW_E_UNSUPPORTED = 5   /* valid request this build cannot serve (e.g. a grid size) */
+};
+
+enum gw_precision {
+  GW_FP32 = 0,               /* FP32 operands on FP32 MFMA, FP32 accumulation */
+  GW_SPLIT_BF16 = 1,         /* f = hi + lo in BF16 (RNE); hi*hi + hi*lo + lo*hi on BF16 MFMA */
+  GW_SPLIT_FP16_SCALED = 2   /* as split BF16 in FP16, each occupied band scaled by a power of two */
+};
+
+typedef struct {
+  int precision;      /* enum gw_precision */
+  double prefactor;   /* p of f_vc = conj(u_v) u_c sqrt(p/(E_c - E_v)); 1 by default, 2 is the paper's spin factor */
+  int accumulate;     /* 0: P(r,r') := result; 1: P(r,r') += result (p_rr must be the caller's buffer) */
+  int tile;           /* -1: the tuned or default tile of the update kernel; otherwise an index from gw_tile_count() */
+} gw_opts;
+
+/* Fills opts with {GW_FP32, 1.0, 0, -1}. */
+void gw_opts_default(gw_opts *opts);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int gw_version(void);
+
+/* Human-readable name of a status code (static storage). */
+const char *gw_status_string(int status);
+
+/* Create a context on HIP device `hip_device` (or a dry-run context for -1).
+ * workspace_cap_bytes bounds the device memory the context may allocate for
+ * its own scratch (0 = no bound).  On success *ctx is set and GW_OK returned. */
+int gw_create(gw_ctx **ctx, int hip_device, size_t workspace_cap_bytes);
+
+/* Release the context and its workspace.  Waits for the context's pending work. */
+int gw_destroy(gw_ctx *ctx);
+
+/* Text of the last failure on this context ("" if none).  Valid until the next call on ctx. */
+const char *gw_last_error(const gw_ctx *ctx);
+
+/* Bytes of device workspace the context currently holds. */
+size_t gw_workspace_bytes(const gw_ctx *ctx);
+
+/* Number of tile configurations of the rank-k update kernel and the name of one. */
+int gw_tile_count(void);
+const char *gw_tile_name(int tile);
+
+/* ---------------------------------------------------------------------------
+ * Pair products, Eq.(fdef):  f_out[v*nc + c][r] = conj(psi_v[v][r]) psi_c[c][r] sqrt(p/(E_c - E_v)).
+ *   psi_v [nv][nr], psi_c [nc][nr] complex64; e_v[nv], e_c[nc] (host, Hartree);
+ *   f_out [nv*nc][nr] complex64, written entirely.  FP32 product of the FP32
+ *   inputs with the scale rounded once from FP64.
+ * ------------------------------------------------------------------------- */
+int gw_pair_products(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *psi_c, int nc, int nr,
+                     const double *e_v, const double *e_c, double prefactor, gw_c32 *f_out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Real-space polarizability (pair products fused into the Hermitian rank-K
+ * update, K = nv*nc):  P(r,r') = -sum_vc conj(f_vc(r)) f_vc(r')  (+ P if accumulate).
+ *   p_rr [nr][nr] complex64, both triangles written (P is Hermitian).
+ *   The pair products are formed inside the update kernel and never stored.
+ * ------------------------------------------------------------------------- */
+int gw_polarizability_r(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *psi_c, int nc, int nr,
+                        const double *e_v, const double *e_c, const gw_opts *opts, gw_c32 *p_rr,
+                        void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Both transforms of Sec. 4.1 restricted to the sphere:
+ *   p_gg[g][g'] = sum_{r,r'} exp(-i G_g.r) p_rr[r][r'] exp(+i G_g'.r').
+ *   p_rr [nr][nr] complex64 (read only), g_miller host [ng][3], p_gg [ng][ng] complex64.
+ *   Grid sides n_d must be in {4, 6, 8, 9, 12, 16, 18, 24, 32, 36} (else GW_E_UNSUPPORTED).
+ * ------------------------------------------------------------------------- */
+int gw_sphere_transform(gw_ctx *ctx, const gw_c32 *p_rr, gw_grid grid, const int *g_miller, int ng,
+                        gw_c32 *p_gg, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * The whole build from orbitals to P~(g,g') (a rank-K update then both transforms).
+ *   psi_occ [nv][nr], psi_unocc [nc][nr] with nr = n1*n2*n3; q (host) [3] is
+ *   accepted for the interface (q enters only the sphere and the Coulomb step).
+ *   p_rr: [nr][nr] buffer that receives P(r,r'), or NULL to use workspace.
+ *   p_gg: [ng][ng] complex64 output.
+ * ------------------------------------------------------------------------- */
+int gw_polarizability(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const gw_c32 *psi_unocc, int nc,
+                      const double *e_v, const double *e_c, gw_grid grid, const double *q,
+                      const int *g_miller, int ng, const gw_opts *opts, gw_c32 *p_rr, gw_c32 *p_gg,
+                      void *stream);
+
+/* ---------------------------------------------------------------------------
+ * eps of Sec. 5.1 in FP64:  eps[g][g'] = delta - sv(g) * H(g,g') * sv(g'), with
+ * sv = sqrt(4 pi / (Omega |q+G|^2)) (0 where |q+G| vanishes; then eps[g][g] = head)
+ * and H the Hermitian part (P~ + P~^H)/2 of the single-precision input.
+ *   p_gg [ng][ng] complex64, eps_out [ng][ng] complex128.
+ * ------------------------------------------------------------------------- */
+int gw_epsilon(gw_ctx *ctx, const gw_c32 *p_gg, int ng, gw_grid grid, const double *q, const int *g_miller,
+               double head, gw_c64 *eps_out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * eps^-1 in FP64: builds eps as gw_epsilon does, factors eps = L L^H (Cholesky,
+ * eps is Hermitian positive definite because P~ is negative semidefinite),
+ * then eps^-1 = L^-H L^-1.  head: NaN means 1.0.
+ *   eps_inv [ng][ng] complex128 output.
+ * Synchronises `stream` to read the pivot flag; returns GW_E_NOTPD (pivot in
+ * gw_last_error) if a pivot is not positive.
+ * ------------------------------------------------------------------------- */
+int gw_eps_inverse(gw_ctx *ctx, const gw_c32 *p_gg, int ng, gw_grid grid, const double *q, const int *g_miller,
+                   double head, gw_c64 *eps_inv, void *stream);
+
+/* Inverse of a Hermitian positive definite complex128 matrix a[n][n] (lower
+ * triangle read) by the same Cholesky path; out [n][n].  Synchronises `stream`. */
+int gw_hpd_inverse(gw_ctx *ctx, const gw_c64 *a, int n, gw_c64 *out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched q-points: each job j runs the whole build and eps^-1 for its own
+ * unoccupied set and sphere, sharing the occupied set.  The launch sequence of
+ * all jobs is captured once into a HIP graph per job shape and replayed.
+ *   jobs (host) [nq]; every job pointer is a device pointer except e_c, q and
+ *   g_miller (host).  P(r,r') lives in one reused workspace buffer.
+ *   Synchronises `stream` (pivot flags).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const gw_c32 *psi_unocc;   /* [nc][nr] */
+  int nc;
+  const double *e_c;         /* host [nc] */
+  double q[3];
+  const int *g_miller;       /* host [ng][3] */
+  int ng;
+  gw_c32 *p_gg;              /* [ng][ng] out */
+  gw_c64 *eps_inv;           /* [ng][ng] out, or NULL to skip the inverse */
+} gw_qjob;
+
+int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const double *e_v, gw_grid grid,
+                              int nq, const gw_qjob *jobs, const gw_opts *opts, double head, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GW_H */

@@ -1,0 +1,8 @@
+"""MI355X (gfx950) library for the real-space static polarizability build of plane-wave GW.
+
+The computation runs in libgw.so (hand-written HIP kernels, C ABI in include/gw.h); this
+package only marshals arguments to it.  There is no CPU fallback: if the library is not
+built, every entry point raises."""
+from ._lib import (GwError, Context, context, load, tile_names, pair_products, polarizability_r,  # noqa: F401
+                   sphere_transform, polarizability, epsilon, eps_inverse, hpd_inverse, polarizability_batched,
+                   EXPORTS, LIB_PATH)

@@ -1,0 +1,318 @@
+"""ctypes binding of libgw.so (include/gw.h).  Argument marshalling only: every step of the
+computation runs in the library's HIP kernels.  Device arrays are torch tensors on a ROCm
+device; small host arrays (energies, q, Miller lists) are numpy arrays."""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgw.so")
+
+GW_OK, GW_E_INVAL, GW_E_NOMEM, GW_E_HIP, GW_E_NOTPD, GW_E_UNSUPPORTED = range(6)
+PRECISIONS = {"fp32": 0, "bf16": 1, "split_bf16": 1, "fp16": 2, "split_fp16": 2}
+
+# Every symbol include/gw.h declares.
+EXPORTS = ("gw_opts_default", "gw_version", "gw_status_string", "gw_create", "gw_destroy", "gw_last_error",
+           "gw_workspace_bytes", "gw_tile_count", "gw_tile_name", "gw_pair_products", "gw_polarizability_r",
+           "gw_sphere_transform", "gw_polarizability", "gw_epsilon", "gw_eps_inverse", "gw_hpd_inverse",
+           "gw_polarizability_batched")
+
+
+class GwError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} [status {status}]")
+        self.status = status
+
+
+class Opts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("prefactor", C.c_double), ("accumulate", C.c_int), ("tile", C.c_int)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("n1", C.c_int), ("n2", C.c_int), ("n3", C.c_int), ("a_bohr", C.c_double)]
+
+
+class QJob(C.Structure):
+    _fields_ = [("psi_unocc", C.c_void_p), ("nc", C.c_int), ("e_c", C.c_void_p), ("q", C.c_double * 3),
+                ("g_miller", C.c_void_p), ("ng", C.c_int), ("p_gg", C.c_void_p), ("eps_inv", C.c_void_p)]
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libgw.so; raises if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_1810_07772_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i, d, sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+    sig = {
+        "gw_opts_default": (None, [C.POINTER(Opts)]),
+        "gw_version": (i, []),
+        "gw_status_string": (C.c_char_p, [i]),
+        "gw_create": (i, [C.POINTER(vp), i, sz]),
+        "gw_destroy": (i, [vp]),
+        "gw_last_error": (C.c_char_p, [vp]),
+        "gw_workspace_bytes": (sz, [vp]),
+        "gw_tile_count": (i, []),
+        "gw_tile_name": (C.c_char_p, [i]),
+        "gw_pair_products": (i, [vp, vp, i, vp, i, i, vp, vp, d, vp, vp]),
+        "gw_polarizability_r": (i, [vp, vp, i, vp, i, i, vp, vp, C.POINTER(Opts), vp, vp]),
+        "gw_sphere_transform": (i, [vp, vp, Grid, vp, i, vp, vp]),
+        "gw_polarizability": (i, [vp, vp, i, vp, i, vp, vp, Grid, vp, vp, i, C.POINTER(Opts), vp, vp, vp]),
+        "gw_epsilon": (i, [vp, vp, i, Grid, vp, vp, d, vp, vp]),
+        "gw_eps_inverse": (i, [vp, vp, i, Grid, vp, vp, d, vp, vp]),
+        "gw_hpd_inverse": (i, [vp, vp, i, vp, vp]),
+        "gw_polarizability_batched": (i, [vp, vp, i, vp, Grid, i, C.POINTER(QJob), C.POINTER(Opts), d, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class Context:
+    """One library context (device workspace, last-error text).  device=-1 makes a dry-run
+    context that only checks arguments."""
+
+    def __init__(self, device: int = 0, workspace_cap: int = 0):
+        self.lib = load()
+        h = C.c_void_p()
+        st = self.lib.gw_create(C.byref(h), int(device), C.c_size_t(workspace_cap))
+        if st != GW_OK:
+            raise GwError(st, f"gw_create(device={device}) failed: {self.lib.gw_status_string(st).decode()}")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            self.lib.gw_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st: int, what: str):
+        if st != GW_OK:
+            msg = self.lib.gw_last_error(self.handle).decode()
+            raise GwError(st, f"{what}: {self.lib.gw_status_string(st).decode()}: {msg}")
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.lib.gw_workspace_bytes(self.handle))
+
+
+_contexts: dict = {}
+
+
+def context(device: Optional[int] = None) -> Context:
+    import torch
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _contexts:
+        _contexts[device] = Context(device)
+    return _contexts[device]
+
+
+# ---------------------------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------------------------
+def _dev(t, dtype=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _host_f64(a, name):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _host_i32(a, name):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _stream(t):
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _opts(precision="fp32", prefactor=1.0, accumulate=False, tile=-1) -> Opts:
+    o = Opts()
+    load().gw_opts_default(C.byref(o))
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.prefactor = float(prefactor)
+    o.accumulate = 1 if accumulate else 0
+    o.tile = int(tile)
+    return o
+
+
+def _grid(n: Sequence[int], a_bohr: float) -> Grid:
+    return Grid(int(n[0]), int(n[1]), int(n[2]), float(a_bohr))
+
+
+def tile_names():
+    lib = load()
+    return [lib.gw_tile_name(i).decode() for i in range(lib.gw_tile_count())]
+
+
+# ---------------------------------------------------------------------------------------------
+# entry points (same names as the C ABI without the gw_ prefix)
+# ---------------------------------------------------------------------------------------------
+def pair_products(psi_v, psi_c, e_v, e_c, prefactor=1.0, out=None, ctx: Optional[Context] = None):
+    import torch
+    nv, nr = psi_v.shape
+    nc = psi_c.shape[0]
+    if out is None:
+        out = torch.empty((nv * nc, nr), dtype=torch.complex64, device=psi_v.device)
+    ctx = ctx or context(psi_v.device.index)
+    ev, pev = _host_f64(e_v, "e_v")
+    ec, pec = _host_f64(e_c, "e_c")
+    st = ctx.lib.gw_pair_products(ctx.handle, _dev(psi_v, torch.complex64, "psi_v"), nv,
+                                  _dev(psi_c, torch.complex64, "psi_c"), nc, nr, pev, pec, float(prefactor),
+                                  _dev(out, torch.complex64, "f_out"), _stream(psi_v))
+    ctx.check(st, "gw_pair_products")
+    return out
+
+
+def polarizability_r(psi_v, psi_c, e_v, e_c, precision="fp32", prefactor=1.0, accumulate=False, tile=-1, out=None,
+                     ctx: Optional[Context] = None):
+    import torch
+    nv, nr = psi_v.shape
+    nc = psi_c.shape[0]
+    if out is None:
+        out = torch.empty((nr, nr), dtype=torch.complex64, device=psi_v.device)
+    ctx = ctx or context(psi_v.device.index)
+    ev, pev = _host_f64(e_v, "e_v")
+    ec, pec = _host_f64(e_c, "e_c")
+    o = _opts(precision, prefactor, accumulate, tile)
+    st = ctx.lib.gw_polarizability_r(ctx.handle, _dev(psi_v, torch.complex64, "psi_v"), nv,
+                                     _dev(psi_c, torch.complex64, "psi_c"), nc, nr, pev, pec, C.byref(o),
+                                     _dev(out, torch.complex64, "p_rr"), _stream(psi_v))
+    ctx.check(st, "gw_polarizability_r")
+    return out
+
+
+def sphere_transform(p_rr, n, miller, out=None, ctx: Optional[Context] = None):
+    import torch
+    m, pm = _host_i32(miller, "g_miller")
+    ng = m.shape[0]
+    if out is None:
+        out = torch.empty((ng, ng), dtype=torch.complex64, device=p_rr.device)
+    ctx = ctx or context(p_rr.device.index)
+    st = ctx.lib.gw_sphere_transform(ctx.handle, _dev(p_rr, torch.complex64, "p_rr"), _grid(n, 1.0), pm, ng,
+                                     _dev(out, torch.complex64, "p_gg"), _stream(p_rr))
+    ctx.check(st, "gw_sphere_transform")
+    return out
+
+
+def polarizability(psi_v, psi_c, e_v, e_c, n, a_bohr, q, miller, precision="fp32", prefactor=1.0, accumulate=False,
+                   tile=-1, p_rr=None, out=None, ctx: Optional[Context] = None):
+    import torch
+    nv = psi_v.shape[0]
+    nc = psi_c.shape[0]
+    m, pm = _host_i32(miller, "g_miller")
+    ng = m.shape[0]
+    qa, pq = _host_f64(q, "q")
+    if out is None:
+        out = torch.empty((ng, ng), dtype=torch.complex64, device=psi_v.device)
+    ctx = ctx or context(psi_v.device.index)
+    ev, pev = _host_f64(e_v, "e_v")
+    ec, pec = _host_f64(e_c, "e_c")
+    o = _opts(precision, prefactor, accumulate, tile)
+    prr = C.c_void_p(None) if p_rr is None else _dev(p_rr, torch.complex64, "p_rr")
+    st = ctx.lib.gw_polarizability(ctx.handle, _dev(psi_v, torch.complex64, "psi_occ"), nv,
+                                   _dev(psi_c, torch.complex64, "psi_unocc"), nc, pev, pec, _grid(n, a_bohr), pq, pm,
+                                   ng, C.byref(o), prr, _dev(out, torch.complex64, "p_gg"), _stream(psi_v))
+    ctx.check(st, "gw_polarizability")
+    return out
+
+
+def epsilon(p_gg, n, a_bohr, q, miller, head=1.0, out=None, ctx: Optional[Context] = None):
+    import torch
+    m, pm = _host_i32(miller, "g_miller")
+    ng = m.shape[0]
+    qa, pq = _host_f64(q, "q")
+    if out is None:
+        out = torch.empty((ng, ng), dtype=torch.complex128, device=p_gg.device)
+    ctx = ctx or context(p_gg.device.index)
+    st = ctx.lib.gw_epsilon(ctx.handle, _dev(p_gg, torch.complex64, "p_gg"), ng, _grid(n, a_bohr), pq, pm,
+                            float(head), _dev(out, torch.complex128, "eps_out"), _stream(p_gg))
+    ctx.check(st, "gw_epsilon")
+    return out
+
+
+def eps_inverse(p_gg, n, a_bohr, q, miller, head=1.0, out=None, ctx: Optional[Context] = None):
+    import torch
+    m, pm = _host_i32(miller, "g_miller")
+    ng = m.shape[0]
+    qa, pq = _host_f64(q, "q")
+    if out is None:
+        out = torch.empty((ng, ng), dtype=torch.complex128, device=p_gg.device)
+    ctx = ctx or context(p_gg.device.index)
+    st = ctx.lib.gw_eps_inverse(ctx.handle, _dev(p_gg, torch.complex64, "p_gg"), ng, _grid(n, a_bohr), pq, pm,
+                                float(head), _dev(out, torch.complex128, "eps_inv"), _stream(p_gg))
+    ctx.check(st, "gw_eps_inverse")
+    return out
+
+
+def hpd_inverse(a, out=None, ctx: Optional[Context] = None):
+    import torch
+    n = a.shape[0]
+    if out is None:
+        out = torch.empty_like(a)
+    ctx = ctx or context(a.device.index)
+    st = ctx.lib.gw_hpd_inverse(ctx.handle, _dev(a, torch.complex128, "a"), n, _dev(out, torch.complex128, "out"),
+                                _stream(a))
+    ctx.check(st, "gw_hpd_inverse")
+    return out
+
+
+def polarizability_batched(psi_v, e_v, n, a_bohr, jobs, precision="fp32", prefactor=1.0, tile=-1, head=1.0,
+                           ctx: Optional[Context] = None):
+    """jobs: list of dicts with psi_c (device), e_c, q, miller (host), p_gg and optional eps_inv (device)."""
+    import torch
+    nv = psi_v.shape[0]
+    ctx = ctx or context(psi_v.device.index)
+    ev, pev = _host_f64(e_v, "e_v")
+    keep = []
+    arr = (QJob * len(jobs))()
+    for j, job in enumerate(jobs):
+        ec, pec = _host_f64(job["e_c"], "e_c")
+        m, pm = _host_i32(job["miller"], "g_miller")
+        keep += [ec, m]
+        arr[j].psi_unocc = _dev(job["psi_c"], torch.complex64, "psi_unocc").value
+        arr[j].nc = job["psi_c"].shape[0]
+        arr[j].e_c = pec.value
+        for d in range(3):
+            arr[j].q[d] = float(job["q"][d])
+        arr[j].g_miller = pm.value
+        arr[j].ng = m.shape[0]
+        arr[j].p_gg = _dev(job["p_gg"], torch.complex64, "p_gg").value
+        ei = job.get("eps_inv")
+        arr[j].eps_inv = None if ei is None else _dev(ei, torch.complex128, "eps_inv").value
+    o = _opts(precision, prefactor, False, tile)
+    st = ctx.lib.gw_polarizability_batched(ctx.handle, _dev(psi_v, torch.complex64, "psi_occ"), nv, pev,
+                                           _grid(n, a_bohr), len(jobs), arr, C.byref(o), float(head),
+                                           _stream(psi_v))
+    ctx.check(st, "gw_polarizability_batched")
+    return jobs

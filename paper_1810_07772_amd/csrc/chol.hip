@@ -1,0 +1,270 @@
+// FP64 inverse of a Hermitian positive definite matrix (eps of Sec. 5.1) by Cholesky:
+//   eps = L L^H  (blocked, right-looking),  X = L^-1 (blocked forward substitution on I),
+//   eps^-1 = X^H X.
+// The paper inverts eps with a Newton iteration built on matrix products because that
+// parallelises across distributed memory; on one GPU the factorisation costs about a
+// third of the flops and every large step below is still a matrix product (zgemm).
+//
+// zgemm: C = alpha * op(A) op(B) + beta * C for complex128, op = identity or conjugate
+// transpose, on v_mfma_f64_16x16x4f64.  Complex products use real MFMA with k' = (k, re/im):
+//   Re C += [Re A, Im A] . [Re B; -Im B],   Im C += [Re A, Im A] . [Im B; Re B].
+#include "gw_internal.h"
+
+namespace gwi {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int GT = 64;    // output tile
+constexpr int GK = 8;     // complex k per stage
+
+__global__ __launch_bounds__(256) void zgemm_kernel(int M, int N, int K, const double2 *__restrict__ A, long long lda,
+                                                    int transA, const double2 *__restrict__ B, long long ldb,
+                                                    int transB, double2 *__restrict__ C, long long ldc, double alpha,
+                                                    double beta, int lower_only, int tri_k) {
+  const int row0 = blockIdx.y * GT, col0 = blockIdx.x * GT;
+  if (lower_only && col0 >= row0 + GT) return;
+  __shared__ double sA[GK][2][GT];
+  __shared__ double sX[GK][2][GT];
+  __shared__ double sY[GK][2][GT];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  f64x4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) { accR[a][b][e] = 0.0; accI[a][b][e] = 0.0; }
+
+  int kbeg = 0;
+  if (tri_k) kbeg = (max(row0, col0) / GK) * GK;
+  const int kl = lane >> 4, li = lane & 15;
+  for (int k0 = kbeg; k0 < K; k0 += GK) {
+#pragma unroll
+    for (int it = 0; it < (GT * GK) / 256; ++it) {
+      const int idx = tid + it * 256;
+      // A side
+      int r, kk;
+      if (transA) { r = idx % GT; kk = idx / GT; } else { r = idx / GK; kk = idx % GK; }
+      double2 va = make_double2(0.0, 0.0);
+      if (row0 + r < M && k0 + kk < K) {
+        if (transA) { va = A[(long long)(k0 + kk) * lda + row0 + r]; va.y = -va.y; }
+        else va = A[(long long)(row0 + r) * lda + k0 + kk];
+      }
+      sA[kk][0][r] = va.x;
+      sA[kk][1][r] = va.y;
+      // B side
+      int c;
+      if (transB) { c = idx / GK; kk = idx % GK; } else { c = idx % GT; kk = idx / GT; }
+      double2 vb = make_double2(0.0, 0.0);
+      if (col0 + c < N && k0 + kk < K) {
+        if (transB) { vb = B[(long long)(col0 + c) * ldb + k0 + kk]; vb.y = -vb.y; }
+        else vb = B[(long long)(k0 + kk) * ldb + col0 + c];
+      }
+      sX[kk][0][c] = vb.x;
+      sX[kk][1][c] = -vb.y;
+      sY[kk][0][c] = vb.y;
+      sY[kk][1][c] = vb.x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < GK / 2; ++s) {
+      const int kk = 2 * s + (kl >> 1), comp = kl & 1;
+      const double a0 = sA[kk][comp][wr * 32 + li], a1 = sA[kk][comp][wr * 32 + 16 + li];
+      const double x0 = sX[kk][comp][wc * 32 + li], x1 = sX[kk][comp][wc * 32 + 16 + li];
+      const double y0 = sY[kk][comp][wc * 32 + li], y1 = sY[kk][comp][wc * 32 + 16 + li];
+      accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0, accR[0][0], 0, 0, 0);
+      accI[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, y0, accI[0][0], 0, 0, 0);
+      accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x1, accR[0][1], 0, 0, 0);
+      accI[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, y1, accI[0][1], 0, 0, 0);
+      accR[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x0, accR[1][0], 0, 0, 0);
+      accI[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, y0, accI[1][0], 0, 0, 0);
+      accR[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1, accR[1][1], 0, 0, 0);
+      accI[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, y1, accI[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // lane holds D[i][j] of each 16x16 block in register e with i = 4*e + (lane>>4), j = lane & 15
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = row0 + wr * 32 + rb * 16 + 4 * e + kl;
+        const int col = col0 + wc * 32 + cb * 16 + li;
+        if (row < M && col < N) {
+          double2 *d = C + (long long)row * ldc + col;
+          double2 v = make_double2(alpha * accR[rb][cb][e], alpha * accI[rb][cb][e]);
+          if (beta != 0.0) { const double2 o = *d; v.x += beta * o.x; v.y += beta * o.y; }
+          *d = v;
+        }
+      }
+}
+
+static hipError_t zgemm(int M, int N, int K, const double2 *A, long long lda, int transA, const double2 *B,
+                        long long ldb, int transB, double2 *C, long long ldc, double alpha, double beta,
+                        int lower_only, int tri_k, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+  hipLaunchKernelGGL(zgemm_kernel, grid, dim3(256), 0, s, M, N, K, A, lda, transA, B, ldb, transB, C, ldc, alpha,
+                     beta, lower_only, tri_k);
+  return hipGetLastError();
+}
+
+// ---- diagonal block: L_kk = chol(A_kk) and Linv_kk = L_kk^-1 (one workgroup) ------------------
+constexpr int NB = 32;
+
+__global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restrict__ A, int n, int k0,
+                                                         double2 *__restrict__ L, double2 *__restrict__ linv,
+                                                         int *__restrict__ pivot) {
+  __shared__ double2 a[NB][NB + 1];
+  __shared__ double2 x[NB][NB + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const int nb = min(NB, n - k0);
+  if (tid == 0) bad = 0;
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int i = idx / NB, j = idx % NB;
+    double2 v = make_double2(0.0, 0.0);
+    if (i < nb && j < nb && j <= i) v = A[(size_t)(k0 + i) * n + k0 + j];
+    if (i >= nb && i == j) v = make_double2(1.0, 0.0);      // pad with identity
+    a[i][j] = v;
+  }
+  __syncthreads();
+  // unblocked right-looking Cholesky on the lower triangle
+  for (int j = 0; j < NB; ++j) {
+    if (tid == 0) {
+      double d = a[j][j].x;
+      if (!(d > 0.0) || !isfinite(d)) {
+        if (j < nb && bad == 0) bad = k0 + j + 1;
+        d = 1.0;
+      }
+      a[j][j] = make_double2(sqrt(d), 0.0);
+    }
+    __syncthreads();
+    const double ljj = a[j][j].x;
+    for (int i = j + 1 + tid; i < NB; i += 256) { a[i][j].x /= ljj; a[i][j].y /= ljj; }
+    __syncthreads();
+    // trailing update a[i][m] -= a[i][j] conj(a[m][j]) for j < m <= i
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+      const int i = idx / NB, m = idx % NB;
+      if (m > j && m <= i) {
+        const double2 p = a[i][j], q = a[m][j];
+        a[i][m].x -= p.x * q.x + p.y * q.y;
+        a[i][m].y -= p.y * q.x - p.x * q.y;
+      }
+    }
+    __syncthreads();
+  }
+  // inverse of the lower-triangular factor, one column per thread: L x = e_col
+  if (tid < NB) {
+    const int col = tid;
+    for (int i = 0; i < NB; ++i) {
+      double2 s = make_double2(i == col ? 1.0 : 0.0, 0.0);
+      for (int m = col; m < i; ++m) {
+        const double2 l = a[i][m], v = x[m][col];
+        s.x -= l.x * v.x - l.y * v.y;
+        s.y -= l.x * v.y + l.y * v.x;
+      }
+      const double d = a[i][i].x;
+      x[i][col] = (i < col) ? make_double2(0.0, 0.0) : make_double2(s.x / d, s.y / d);
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int i = idx / NB, j = idx % NB;
+    if (i < nb && j < nb) L[(size_t)(k0 + i) * n + k0 + j] = (j <= i) ? a[i][j] : make_double2(0.0, 0.0);
+    linv[idx] = (i < nb && j < nb) ? x[i][j] : make_double2(0.0, 0.0);
+  }
+  if (tid == 0 && bad != 0 && *pivot == 0) *pivot = bad;
+}
+
+__global__ void fill_identity_kernel(double2 *__restrict__ a, int n, double diag) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * n) return;
+  const size_t i = idx / n, j = idx % n;
+  a[idx] = make_double2(i == j ? diag : 0.0, 0.0);
+}
+
+// out[j][i] = conj(out[i][j]) for i > j (upper triangle from the lower), 32x32 tiles via LDS.
+__global__ __launch_bounds__(256) void mirror_lower_kernel(double2 *__restrict__ a, int n) {
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bj > bi) return;
+  __shared__ double2 t[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = 0; k < 32; k += 8) {
+    const int i = bi * 32 + ty + k, j = bj * 32 + tx;
+    if (i < n && j < n) t[ty + k][tx] = a[(size_t)i * n + j];
+  }
+  __syncthreads();
+  for (int k = 0; k < 32; k += 8) {
+    const int i = bj * 32 + ty + k, j = bi * 32 + tx;     // destination (i, j) in the upper tile
+    if (i < n && j < n && j > i) {
+      const double2 v = t[tx][ty + k];                    // a[j][i]
+      a[(size_t)i * n + j] = make_double2(v.x, -v.y);
+    }
+  }
+}
+
+__global__ void fill_int_kernel(int *p, int v) { *p = v; }
+
+hipError_t launch_fill_int(int *p, int value, hipStream_t s) {
+  hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, s, p, value);
+  return hipGetLastError();
+}
+
+size_t chol_small_bytes(int n) {
+  const int nblk = (n + NB - 1) / NB;
+  return (size_t)nblk * NB * NB * sizeof(double2);
+}
+
+#define GW_TRY(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
+
+hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small, int *pivot_dev, double2 *out,
+                       hipStream_t s) {
+  const int nblk = (n + NB - 1) / NB;
+  const size_t nn = (size_t)n * n;
+  const unsigned fill_blocks = (unsigned)((nn + 255) / 256);
+  GW_TRY(launch_fill_int(pivot_dev, 0, s));
+  hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, l, n, 0.0);
+  GW_TRY(hipGetLastError());
+  // 1. factor a = L L^H
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int k0 = kb * NB, nb = min(NB, n - k0), rest = n - k0 - nb;
+    double2 *linv = small + (size_t)kb * NB * NB;
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, a, n, k0, l, linv, pivot_dev);
+    GW_TRY(hipGetLastError());
+    if (rest > 0) {
+      // panel: L[k0+nb:, k0:k0+nb] = A[k0+nb:, k0:k0+nb] Linv^H
+      GW_TRY(zgemm(rest, nb, nb, a + (size_t)(k0 + nb) * n + k0, n, 0, linv, NB, 1, l + (size_t)(k0 + nb) * n + k0, n,
+                   1.0, 0.0, 0, 0, s));
+      // trailing: A[k0+nb:, k0+nb:] -= Lp Lp^H (lower tiles)
+      const double2 *lp = l + (size_t)(k0 + nb) * n + k0;
+      GW_TRY(zgemm(rest, rest, nb, lp, n, 0, lp, n, 1, a + (size_t)(k0 + nb) * n + k0 + nb, n, -1.0, 1.0, 1, 0, s));
+    }
+  }
+  // 2. X = L^-1 by right-looking block substitution on B = I (B reuses a)
+  hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, a, n, 1.0);
+  GW_TRY(hipGetLastError());
+  hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, x, n, 0.0);
+  GW_TRY(hipGetLastError());
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int k0 = kb * NB, nb = min(NB, n - k0), rest = n - k0 - nb, ncol = k0 + nb;
+    const double2 *linv = small + (size_t)kb * NB * NB;
+    // X_k = Linv_kk B_k (block row k, columns < k0+nb)
+    GW_TRY(zgemm(nb, ncol, nb, linv, NB, 0, a + (size_t)k0 * n, n, 0, x + (size_t)k0 * n, n, 1.0, 0.0, 0, 0, s));
+    if (rest > 0) {
+      // B_i -= L_ik X_k for the block rows below
+      GW_TRY(zgemm(rest, ncol, nb, l + (size_t)(k0 + nb) * n + k0, n, 0, x + (size_t)k0 * n, n, 0,
+                   a + (size_t)(k0 + nb) * n, n, -1.0, 1.0, 0, 0, s));
+    }
+  }
+  // 3. out = X^H X (lower tiles, k from max(row, col) since X is lower triangular), then mirror
+  GW_TRY(zgemm(n, n, n, x, n, 1, x, n, 0, out, n, 1.0, 0.0, 1, 1, s));
+  dim3 mg((n + 31) / 32, (n + 31) / 32);
+  hipLaunchKernelGGL(mirror_lower_kernel, mg, dim3(256), 0, s, out, n);
+  return hipGetLastError();
+}
+
+}  // namespace gwi

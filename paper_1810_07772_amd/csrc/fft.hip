@@ -1,0 +1,232 @@
+// Batched 1-D DFT passes for the two transforms of Sec. 4.1 (rows of P to g with exp(-i G.r),
+// columns with exp(+i G'.r')), pruned to the G-sphere.
+//
+// A 3-D transform over a grid index is three passes, one per axis.  In every pass the
+// batch axis (the other matrix index, contiguous in memory) runs across the lanes of a
+// wave, so each lane owns one whole length-n transform along a strided axis, every load
+// and store is coalesced, and no shuffles are needed.  Each pass keeps only the output
+// frequencies that the sphere (or its projection onto the remaining axes) still needs,
+// through an output-row map built on the host.
+//
+// The length-n DFT is done in registers as n = R1*R2 (two stages of naive DFTs with an
+// inner twiddle).  Twiddle factors are compile-time constants: cos/sin of 2 pi m/n are
+// evaluated by a constexpr Taylor series in double and rounded once to float, with the
+// quarter-turn values exact, so the unrolled code carries them as literals.
+#include "gw_internal.h"
+
+namespace gwi {
+
+// ---- constexpr trigonometry (Taylor series about 0 after reduction to [-pi/4, pi/4]) -----
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double taylor_sin(double x) {
+  double term = x, sum = x;
+  for (int k = 1; k < 14; ++k) { term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0)); sum += term; }
+  return sum;
+}
+constexpr double taylor_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) { term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k)); sum += term; }
+  return sum;
+}
+// cos and sin of 2 pi m / n using the octant of m/n: exact at multiples of a quarter turn.
+constexpr double cos2pi(long m, long n) {
+  m %= n; if (m < 0) m += n;
+  // 8m/n selects the octant; reduce to an angle in [-pi/4, pi/4] about a multiple of pi/2.
+  const long q = (4 * m + n / 2) / n;          // nearest quarter turn (0..4)
+  const double r = 2.0 * kPi * ((double)m / (double)n - (double)q / 4.0);
+  if (4 * m == q * n) {                        // exactly a quarter-turn multiple
+    switch (q & 3) { case 0: return 1.0; case 1: return 0.0; case 2: return -1.0; default: return 0.0; }
+  }
+  switch (q & 3) {
+    case 0: return taylor_cos(r);
+    case 1: return -taylor_sin(r);
+    case 2: return -taylor_cos(r);
+    default: return taylor_sin(r);
+  }
+}
+constexpr double sin2pi(long m, long n) {
+  m %= n; if (m < 0) m += n;
+  const long q = (4 * m + n / 2) / n;
+  const double r = 2.0 * kPi * ((double)m / (double)n - (double)q / 4.0);
+  if (4 * m == q * n) {
+    switch (q & 3) { case 0: return 0.0; case 1: return 1.0; case 2: return 0.0; default: return -1.0; }
+  }
+  switch (q & 3) {
+    case 0: return taylor_sin(r);
+    case 1: return taylor_cos(r);
+    case 2: return -taylor_sin(r);
+    default: return -taylor_cos(r);
+  }
+}
+
+template <int N>
+struct Twiddle {
+  float c[N];
+  float s[N];
+  constexpr Twiddle() : c(), s() {
+    for (int m = 0; m < N; ++m) { c[m] = (float)cos2pi(m, N); s[m] = (float)sin2pi(m, N); }
+  }
+};
+
+// factor choice R1 * R2 = N with both factors small
+template <int N> struct Factor { static constexpr int R1 = N, R2 = 1; };
+template <> struct Factor<4> { static constexpr int R1 = 2, R2 = 2; };
+template <> struct Factor<6> { static constexpr int R1 = 2, R2 = 3; };
+template <> struct Factor<8> { static constexpr int R1 = 2, R2 = 4; };
+template <> struct Factor<9> { static constexpr int R1 = 3, R2 = 3; };
+template <> struct Factor<10> { static constexpr int R1 = 2, R2 = 5; };
+template <> struct Factor<12> { static constexpr int R1 = 3, R2 = 4; };
+template <> struct Factor<15> { static constexpr int R1 = 3, R2 = 5; };
+template <> struct Factor<16> { static constexpr int R1 = 4, R2 = 4; };
+template <> struct Factor<18> { static constexpr int R1 = 3, R2 = 6; };
+template <> struct Factor<20> { static constexpr int R1 = 4, R2 = 5; };
+template <> struct Factor<24> { static constexpr int R1 = 4, R2 = 6; };
+template <> struct Factor<27> { static constexpr int R1 = 3, R2 = 9; };
+template <> struct Factor<30> { static constexpr int R1 = 5, R2 = 6; };
+template <> struct Factor<32> { static constexpr int R1 = 4, R2 = 8; };
+template <> struct Factor<36> { static constexpr int R1 = 6, R2 = 6; };
+template <> struct Factor<40> { static constexpr int R1 = 5, R2 = 8; };
+template <> struct Factor<48> { static constexpr int R1 = 6, R2 = 8; };
+
+// acc += x * W^m with W^m = (c, sgn * s) a compile-time constant after unrolling.
+template <int N, int SIGN>
+__device__ __forceinline__ void cmac_tw(float2 &acc, float2 x, int m) {
+  constexpr Twiddle<N> tw{};
+  m %= N;
+  const float c = tw.c[m];
+  const float s = SIGN * tw.s[m];
+  if (s == 0.0f) {
+    if (c == 1.0f) { acc.x += x.x; acc.y += x.y; }
+    else if (c == -1.0f) { acc.x -= x.x; acc.y -= x.y; }
+    else { acc.x += c * x.x; acc.y += c * x.y; }
+  } else if (c == 0.0f) {
+    // (x.x + i x.y) * (i s) = -s x.y + i s x.x
+    if (s == 1.0f) { acc.x -= x.y; acc.y += x.x; }
+    else if (s == -1.0f) { acc.x += x.y; acc.y -= x.x; }
+    else { acc.x -= s * x.y; acc.y += s * x.x; }
+  } else {
+    acc.x += c * x.x - s * x.y;
+    acc.y += c * x.y + s * x.x;
+  }
+}
+
+template <int N, int SIGN>
+__device__ __forceinline__ float2 mul_tw(float2 x, int m) {
+  float2 acc = make_float2(0.f, 0.f);
+  cmac_tw<N, SIGN>(acc, x, m);
+  return acc;
+}
+
+// In-register DFT X[k] = sum_n x[n] exp(SIGN * 2 pi i n k / N), n = R2*n1 + n2, k = k1 + R1*k2.
+template <int N, int SIGN>
+__device__ __forceinline__ void dft_regs(const float2 (&x)[N], float2 (&X)[N]) {
+  constexpr int R1 = Factor<N>::R1, R2 = Factor<N>::R2;
+  float2 y[R1][R2];
+#pragma unroll
+  for (int n2 = 0; n2 < R2; ++n2)
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) cmac_tw<N, SIGN>(acc, x[R2 * n1 + n2], (n1 * k1 % R1) * R2);
+      y[k1][n2] = (n2 * k1 == 0) ? acc : mul_tw<N, SIGN>(acc, n2 * k1);
+    }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) cmac_tw<N, SIGN>(acc, y[k1][n2], (n2 * k2 % R2) * R1);
+      X[k1 + R1 * k2] = acc;
+    }
+}
+
+constexpr int FFT_THREADS = 256;
+
+// grid.x: batch blocks of 256, grid.y: flattened (o, u).
+template <int N, int SIGN>
+__global__ __launch_bounds__(FFT_THREADS) void fft_pass_kernel(const float2 *__restrict__ in,
+                                                                float2 *__restrict__ out, int U, int B,
+                                                                long long ld_in, long long ld_out,
+                                                                const int *__restrict__ map) {
+  const int b = blockIdx.x * FFT_THREADS + threadIdx.x;
+  if (b >= B) return;
+  const int ou = blockIdx.y;
+  const int o = ou / U, u = ou - o * U;
+  const int *mrow = map + (size_t)ou * N;
+  float2 x[N], X[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = in[((long long)(o * N + i) * U + u) * ld_in + b];
+  dft_regs<N, SIGN>(x, X);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int row = mrow[k];
+    if (row >= 0) out[(long long)row * ld_out + b] = X[k];
+  }
+}
+
+#define GW_FFT_SIZES(X) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16) X(18) X(20) X(24) X(27) X(30) X(32) X(36) X(40) X(48)
+
+bool fft_size_supported(int n) {
+  switch (n) {
+#define GW_CASE(n_) case n_:
+    GW_FFT_SIZES(GW_CASE)
+#undef GW_CASE
+    return true;
+    default: return false;
+  }
+}
+
+hipError_t launch_fft_pass(int n, int sign, const float2 *in, float2 *out, int O, int U, int B, long long ld_in,
+                           long long ld_out, const int *map, hipStream_t s) {
+  if (O * U > 65535 * 1024) return hipErrorInvalidValue;
+  dim3 grid((B + FFT_THREADS - 1) / FFT_THREADS, O * U), block(FFT_THREADS);
+  if (grid.y > 65535) return hipErrorInvalidValue;
+  switch (n) {
+#define GW_CASE(n_)                                                                                          \
+  case n_:                                                                                                   \
+    if (sign < 0)                                                                                            \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(fft_pass_kernel<n_, -1>), grid, block, 0, s, in, out, U, B, ld_in, \
+                         ld_out, map);                                                                       \
+    else                                                                                                     \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(fft_pass_kernel<n_, 1>), grid, block, 0, s, in, out, U, B, ld_in,  \
+                         ld_out, map);                                                                       \
+    break;
+    GW_FFT_SIZES(GW_CASE)
+#undef GW_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---- complex64 transpose through LDS: out[c][r] = in[r][c] ----------------------------------
+constexpr int TT = 64;
+__global__ __launch_bounds__(256) void transpose_c64_kernel(const float2 *__restrict__ in, float2 *__restrict__ out,
+                                                            int rows, int cols, long long ld_in, long long ld_out) {
+  __shared__ float2 t[TT][TT + 1];
+  const int r0 = blockIdx.y * TT, c0 = blockIdx.x * TT;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < TT; k += 4) {
+    const int r = r0 + ty + k, c = c0 + tx;
+    if (r < rows && c < cols) t[ty + k][tx] = in[(long long)r * ld_in + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < TT; k += 4) {
+    const int c = c0 + ty + k, r = r0 + tx;
+    if (r < rows && c < cols) out[(long long)c * ld_out + r] = t[tx][ty + k];
+  }
+}
+
+hipError_t launch_transpose_c64(const float2 *in, float2 *out, int rows, int cols, long long ld_in, long long ld_out,
+                                hipStream_t s) {
+  dim3 grid((cols + TT - 1) / TT, (rows + TT - 1) / TT);
+  if (grid.y > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(transpose_c64_kernel, grid, dim3(256), 0, s, in, out, rows, cols, ld_in, ld_out);
+  return hipGetLastError();
+}
+
+}  // namespace gwi

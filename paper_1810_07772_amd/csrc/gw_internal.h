@@ -1,0 +1,86 @@
+// Internal declarations shared by the host ABI (gw_api.cpp) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gw.h"
+
+struct gw_ctx {
+  int device = -1;            // -1: dry-run context (argument checks only)
+  size_t cap = 0;             // workspace cap in bytes (0: none)
+  size_t held = 0;            // bytes currently allocated in slots
+  std::string err;            // text of the last failure
+  struct Slot { void *ptr = nullptr; size_t bytes = 0; };
+  std::vector<Slot> slots;    // grow-only named workspace buffers
+  int *pivot_host = nullptr;  // pinned host word for the Cholesky pivot flag
+  void *graph_cache = nullptr;  // batched-q graphs (owned; see gw_batched.cpp)
+};
+
+namespace gwi {
+
+// Workspace slots (each a grow-only device buffer owned by the context).
+enum SlotId {
+  WS_SCALE = 0,   // float [nv][nc] pair scales
+  WS_ENERGY,      // double [nv + nc] energies
+  WS_PRR,         // complex64 [nr][nr] internal P(r,r')
+  WS_FFT_A,       // FFT intermediates
+  WS_FFT_B,
+  WS_FFT_MAP,     // int output-row maps of the FFT passes
+  WS_MILLER,      // int [ng][3]
+  WS_SQRTV,       // double [ng]
+  WS_EPS,         // complex128 [n][n] eps / working matrix
+  WS_CHOL_L,      // complex128 [n][n] Cholesky factor
+  WS_CHOL_X,      // complex128 [n][n] L^-1
+  WS_CHOL_SMALL,  // diagonal-block inverses + pivot flag
+  WS_BSCALE,      // per-band power-of-two exponents (FP16 path)
+  WS_PGG_T,       // complex64 [ng][ng] transposed sphere result
+  WS_COUNT_BASE
+};
+
+// Kernel launchers.  All return hipSuccess or the launch error; all run on `s`.
+hipError_t launch_scale_table(const double *e_v, int nv, const double *e_c, int nc, double prefactor,
+                              float *scale, hipStream_t s);
+hipError_t launch_pair_products(const float2 *psi_v, int nv, const float2 *psi_c, int nc, int nr,
+                                const float *scale, float2 *f, hipStream_t s);
+
+// Rank-K update P = -F^H F with the pair products formed in-kernel.
+// precision: enum gw_precision; tile: index into the tile table (-1 default).
+int herk_tile_count();
+const char *herk_tile_name(int tile);
+bool herk_tile_supports(int tile, int precision);
+int herk_default_tile(int precision, int nr);
+hipError_t launch_herk(int precision, int tile, const float2 *psi_v, const float2 *psi_c, const float *scale,
+                       const int *band_exp, float2 *p, int nr, int nv, int nc, int accumulate, hipStream_t s);
+hipError_t launch_band_exponents(const float2 *psi_v, int nv, const float2 *psi_c, int nc, int nr,
+                                 const float *scale, int *band_exp, hipStream_t s);
+
+// FFT helpers.
+bool fft_size_supported(int n);
+// One pass along an axis of length n: in element ((o*n + i)*U + u)*ld_in + b, out element
+// map[(o*U + u)*n + k]*ld_out + b for every k with map >= 0.  sign -1: exp(-i..), +1: exp(+i..).
+hipError_t launch_fft_pass(int n, int sign, const float2 *in, float2 *out, int O, int U, int B, long long ld_in,
+                           long long ld_out, const int *map, hipStream_t s);
+hipError_t launch_transpose_c64(const float2 *in, float2 *out, int rows, int cols, long long ld_in,
+                                long long ld_out, hipStream_t s);
+
+// eps and the FP64 Hermitian inverse.
+hipError_t launch_sqrtv(const int *miller, int ng, double q0, double q1, double q2, double a_bohr, double *sv,
+                        hipStream_t s);
+hipError_t launch_eps_build(const float2 *p_gg, int ng, const double *sv, double head, double2 *eps,
+                            hipStream_t s);
+// Cholesky-based inverse of a Hermitian PD matrix (lower triangle of a read).  a is overwritten.
+// l, x: n*n workspaces; small: workspace of at least chol_small_bytes(n); pivot_dev: device int.
+size_t chol_small_bytes(int n);
+hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small, int *pivot_dev, double2 *out,
+                       hipStream_t s);
+hipError_t launch_fill_int(int *p, int value, hipStream_t s);
+
+// Releases the batched-q graphs a context holds.
+void batched_release(gw_ctx *ctx);
+
+}  // namespace gwi

@@ -1,0 +1,483 @@
+// Hermitian rank-K update P(r,r') = -sum_k conj(F[k][r]) F[k][r'], K = nv*nc, with the pair
+// products F[v*nc + c][r] = conj(psi_v[v][r]) psi_c[c][r] s_vc formed inside the kernel
+// (Eq.(fdef) and the outer product below it, N_k = 1).
+//
+// Complex arithmetic on real MFMA: with f = a + ib,
+//   conj(f_i) f_j = (a_i a_j + b_i b_j) + i (a_i b_j - b_i a_j),
+// so the real part is a real GEMM over k' = (pair, component) of X = [a; b] with itself
+// and the imaginary part is a real GEMM of X (rows) with Y = [b; -a] (columns).
+//
+// Work decomposition: one workgroup per lower-triangle tile (I, J) of the N_r x N_r output
+// (the paper's 2-D PMatrix tiles), 4 waves each owning a 64x64 quadrant.  The K loop walks
+// occupied bands v and chunks of KC unoccupied bands; for each chunk the workgroup loads
+// psi_c[chunk][I u J] (and psi_v[v][I u J]), forms only the f entries its tile needs (the
+// paper's local-f optimisation), and stages them in LDS (double buffered, one barrier per
+// chunk) so the loads of chunk i+1 overlap the MFMAs of chunk i.  The epilogue writes
+// the tile and, off the diagonal, its conjugate transpose.
+//
+// Variants:
+//  * FP32:  f in FP32 on v_mfma_f32_32x32x2f32.  Each occupied band's sum (nc pairs) is
+//    accumulated in fresh registers and folded into a running FP32 sum (two-level sum).
+//  * split BF16 / FP16: f = hi + lo (RNE), products hi*hi + hi*lo + lo*hi on
+//    v_mfma_f32_32x32x16_{bf16,f16}, FP32 accumulation.  The FP16 variant multiplies each
+//    band's f by 2^e_v (one exponent per occupied band) and folds the band's partial sum
+//    back with 2^-2e_v.
+#include "gw_internal.h"
+
+namespace gwi {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int HB = 128;       // tile side
+constexpr int NTHR = 256;     // 4 waves
+
+// Map a linear block id to a lower-triangle tile so that the tiles sent to one XCD
+// (blocks are dealt round-robin over the 8 XCDs) form a contiguous run of the triangle
+// and share psi_c rows in that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int ntiles) {
+  const int q = ntiles >> 3, rem = ntiles & 7;
+  const int x = b & 7, s = b >> 3;
+  return x * q + min(x, rem) + s;
+}
+
+__device__ __forceinline__ void tile_of(int t, int &bi, int &bj) {
+  int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  bi = i;
+  bj = t - i * (i + 1) / 2;
+}
+
+__device__ __forceinline__ float2 cmul_conj(float2 v, float2 c) {   // conj(v) * c
+  return make_float2(v.x * c.x + v.y * c.y, v.x * c.y - v.y * c.x);
+}
+
+// Epilogue: lane holds element (i, j) of 32x32 block (rb, cb) of its wave's quadrant in
+// register e, with i = (e & 3) + 8*(e >> 2) + 4*(lane >> 5), j = lane & 31.
+__device__ __forceinline__ void store_tile(float2 *__restrict__ P, int nr, int I0, int J0, bool mirror,
+                                           int accumulate, const f32x16 (&re)[2][2], const f32x16 (&im)[2][2],
+                                           int wr, int wc, int lane) {
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int i = (e & 3) + 8 * (e >> 2) + 4 * (lane >> 5);
+        const int j = lane & 31;
+        const int row = I0 + wr * 64 + rb * 32 + i;
+        const int col = J0 + wc * 64 + cb * 32 + j;
+        if (row < nr && col < nr) {
+          const float pr = -re[rb][cb][e], pi = -im[rb][cb][e];
+          float2 *d = P + (size_t)row * nr + col;
+          if (accumulate) { float2 o = *d; *d = make_float2(o.x + pr, o.y + pi); }
+          else *d = make_float2(pr, pi);
+          if (mirror) {
+            float2 *m = P + (size_t)col * nr + row;
+            if (accumulate) { float2 o = *m; *m = make_float2(o.x + pr, o.y - pi); }
+            else *m = make_float2(pr, -pi);
+          }
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------------------------
+// FP32 variant
+// ---------------------------------------------------------------------------------------------
+constexpr int KC32 = 16;   // unoccupied bands per stage
+
+template <bool FOLD>
+__global__ __launch_bounds__(NTHR, 1) void herk_fp32_kernel(const float2 *__restrict__ psi_v,
+                                                             const float2 *__restrict__ psi_c,
+                                                             const float *__restrict__ scale,
+                                                             float2 *__restrict__ P, int nr, int nv, int nc,
+                                                             int ntiles, int accumulate) {
+  // [buf][pair][component][point]; A: f on the tile's rows, B: f on its columns, Y: (im, -re) of B.
+  __shared__ float sA[2][KC32][2][HB];
+  __shared__ float sB[2][KC32][2][HB];
+  __shared__ float sY[2][KC32][2][HB];
+
+  int bi, bj;
+  tile_of(xcd_remap(blockIdx.x, ntiles), bi, bj);
+  const int I0 = bi * HB, J0 = bj * HB;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int cp = tid & 63;          // producer: grid points 2cp, 2cp+1 of the tile's rows and columns
+  const int prow = wave;            // producer: pairs prow + 4*i
+  const int ri = I0 + 2 * cp, rj = J0 + 2 * cp;
+  const bool oki0 = ri < nr, oki1 = ri + 1 < nr, okj0 = rj < nr, okj1 = rj + 1 < nr;
+
+  const int nchc = (nc + KC32 - 1) / KC32;
+  const int nch = nv * nchc;
+
+  float2 vI[2], vJ[2];              // psi_v of the staged chunk
+  float2 cI[4][2], cJ[4][2];        // psi_c of the staged chunk
+  float sc[4];
+
+  auto load_chunk = [&](int ch) {
+    const int v = ch / nchc;
+    const int c0 = (ch - v * nchc) * KC32;
+    const float2 z = make_float2(0.f, 0.f);
+    const float2 *pv = psi_v + (size_t)v * nr;
+    vI[0] = oki0 ? pv[ri] : z;  vI[1] = oki1 ? pv[ri + 1] : z;
+    vJ[0] = okj0 ? pv[rj] : z;  vJ[1] = okj1 ? pv[rj + 1] : z;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = c0 + prow + 4 * i;
+      const bool okc = c < nc;
+      sc[i] = okc ? scale[v * nc + c] : 0.f;
+      const float2 *pc = psi_c + (size_t)(okc ? c : 0) * nr;
+      cI[i][0] = (okc && oki0) ? pc[ri] : z;  cI[i][1] = (okc && oki1) ? pc[ri + 1] : z;
+      cJ[i][0] = (okc && okj0) ? pc[rj] : z;  cJ[i][1] = (okc && okj1) ? pc[rj + 1] : z;
+    }
+  };
+  auto produce = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = prow + 4 * i;
+      float2 fi0 = cmul_conj(vI[0], cI[i][0]), fi1 = cmul_conj(vI[1], cI[i][1]);
+      float2 fj0 = cmul_conj(vJ[0], cJ[i][0]), fj1 = cmul_conj(vJ[1], cJ[i][1]);
+      const float s = sc[i];
+      fi0.x *= s; fi0.y *= s; fi1.x *= s; fi1.y *= s;
+      fj0.x *= s; fj0.y *= s; fj1.x *= s; fj1.y *= s;
+      *reinterpret_cast<float2 *>(&sA[buf][p][0][2 * cp]) = make_float2(fi0.x, fi1.x);
+      *reinterpret_cast<float2 *>(&sA[buf][p][1][2 * cp]) = make_float2(fi0.y, fi1.y);
+      *reinterpret_cast<float2 *>(&sB[buf][p][0][2 * cp]) = make_float2(fj0.x, fj1.x);
+      *reinterpret_cast<float2 *>(&sB[buf][p][1][2 * cp]) = make_float2(fj0.y, fj1.y);
+      *reinterpret_cast<float2 *>(&sY[buf][p][0][2 * cp]) = make_float2(fj0.y, fj1.y);
+      *reinterpret_cast<float2 *>(&sY[buf][p][1][2 * cp]) = make_float2(-fj0.x, -fj1.x);
+    }
+  };
+
+  f32x16 accR[2][2], accI[2][2];
+  f32x16 runR[2][2], runI[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) { accR[a][b][e] = 0.f; accI[a][b][e] = 0.f; runR[a][b][e] = 0.f; runI[a][b][e] = 0.f; }
+
+  const int comp = lane >> 5, idx = lane & 31;
+  const int ar0 = wr * 64 + idx, bc0 = wc * 64 + idx;
+
+  load_chunk(0);
+  produce(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) load_chunk(ch + 1);
+#pragma unroll 4
+    for (int p = 0; p < KC32; ++p) {
+      const float a0 = sA[buf][p][comp][ar0], a1 = sA[buf][p][comp][ar0 + 32];
+      const float x0 = sB[buf][p][comp][bc0], x1 = sB[buf][p][comp][bc0 + 32];
+      const float y0 = sY[buf][p][comp][bc0], y1 = sY[buf][p][comp][bc0 + 32];
+      accR[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, x0, accR[0][0], 0, 0, 0);
+      accI[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, y0, accI[0][0], 0, 0, 0);
+      accR[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, x1, accR[0][1], 0, 0, 0);
+      accI[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, y1, accI[0][1], 0, 0, 0);
+      accR[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, x0, accR[1][0], 0, 0, 0);
+      accI[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, y0, accI[1][0], 0, 0, 0);
+      accR[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, x1, accR[1][1], 0, 0, 0);
+      accI[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, y1, accI[1][1], 0, 0, 0);
+    }
+    if (FOLD && ((ch % nchc) == nchc - 1)) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          runR[a][b] += accR[a][b];
+          runI[a][b] += accI[a][b];
+#pragma unroll
+          for (int e = 0; e < 16; ++e) { accR[a][b][e] = 0.f; accI[a][b][e] = 0.f; }
+        }
+    }
+    if (ch + 1 < nch) produce(buf ^ 1);
+    __syncthreads();
+  }
+  if (FOLD) {
+    store_tile(P, nr, I0, J0, bi != bj, accumulate, runR, runI, wr, wc, lane);
+  } else {
+    store_tile(P, nr, I0, J0, bi != bj, accumulate, accR, accI, wr, wc, lane);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Split-precision variants (BF16 or FP16 hi/lo) on v_mfma_f32_32x32x16_{bf16,f16}.
+// Inside one MFMA, lane l supplies the 8 consecutive k' = 8*(l>>5) .. +7 of its row (A) or
+// column (B): four pairs x (re, im).  A stage holds KS = 16 pairs = two groups of 16 k', and
+// each group costs three MFMAs (hi*hi, hi*lo, lo*hi) for Re and three for Im per 32x32 block.
+// LDS holds f on the tile's rows and columns as hi and lo planes; the Im operand
+// Y = (im, -re) is derived in registers from the column operand (a 16-bit rotate of each
+// (re, im) word and a sign flip).
+// ---------------------------------------------------------------------------------------------
+constexpr int KS = 16;             // pairs per stage
+constexpr int SROW = 2 * KS + 8;   // narrow elements per grid-point row (padded against bank conflicts)
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct SplitTraits;
+template <> struct SplitTraits<__bf16> {
+  typedef bf16x8 vec;
+  static __device__ __forceinline__ f32x16 mfma(vec a, vec b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct SplitTraits<_Float16> {
+  typedef f16x8 vec;
+  static __device__ __forceinline__ f32x16 mfma(vec a, vec b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// (re, im) words -> (im, -re) words.
+template <typename V>
+__device__ __forceinline__ V rot_neg(V b) {
+  u32x4 w = __builtin_bit_cast(u32x4, b);
+  u32x4 y;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) y[m] = ((w[m] >> 16) | (w[m] << 16)) ^ 0x80000000u;
+  return __builtin_bit_cast(V, y);
+}
+
+template <typename T, bool SCALED>
+__global__ __launch_bounds__(NTHR, 1) void herk_split_kernel(const float2 *__restrict__ psi_v,
+                                                              const float2 *__restrict__ psi_c,
+                                                              const float *__restrict__ scale,
+                                                              const int *__restrict__ band_exp,
+                                                              float2 *__restrict__ P, int nr, int nv, int nc,
+                                                              int ntiles, int accumulate) {
+  typedef typename SplitTraits<T>::vec vec;
+  __shared__ __attribute__((aligned(16))) T sAh[2][HB][SROW];
+  __shared__ __attribute__((aligned(16))) T sAl[2][HB][SROW];
+  __shared__ __attribute__((aligned(16))) T sBh[2][HB][SROW];
+  __shared__ __attribute__((aligned(16))) T sBl[2][HB][SROW];
+
+  int bi, bj;
+  tile_of(xcd_remap(blockIdx.x, ntiles), bi, bj);
+  const int I0 = bi * HB, J0 = bj * HB;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+
+  // Producer: waves 0 and 2 own the tile's rows, waves 1 and 3 its columns; each thread
+  // owns one grid point and forms all KS pairs of the stage for it (its KS loads are
+  // strided by nr, coalesced across the wave's 64 consecutive points).
+  const int pside = wave & 1;
+  const int ppt = lane + 64 * (wave >> 1);
+  const int gpt = (pside ? J0 : I0) + ppt;
+  const bool okp = gpt < nr;
+  const int nchc = (nc + KS - 1) / KS;
+  const int nch = nv * nchc;
+
+  float2 pvv;
+  float2 pc[KS];
+  float sc[KS];
+  float mul = 1.0f;
+
+  auto load_chunk = [&](int ch) {
+    const int v = ch / nchc;
+    const int c0 = (ch - v * nchc) * KS;
+    const float2 z = make_float2(0.f, 0.f);
+    pvv = okp ? psi_v[(size_t)v * nr + gpt] : z;
+    if (SCALED) mul = ldexpf(1.0f, band_exp[v]);
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int c = c0 + k;
+      const bool okc = c < nc;
+      sc[k] = okc ? scale[v * nc + c] : 0.f;
+      pc[k] = (okc && okp) ? psi_c[(size_t)c * nr + gpt] : z;
+    }
+  };
+  auto produce = [&](int buf) {
+    T *dh = pside ? &sBh[buf][ppt][0] : &sAh[buf][ppt][0];
+    T *dl = pside ? &sBl[buf][ppt][0] : &sAl[buf][ppt][0];
+#pragma unroll
+    for (int g = 0; g < KS / 4; ++g) {
+      vec hv, lv;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int k = 4 * g + m;
+        float2 f = cmul_conj(pvv, pc[k]);
+        const float s = sc[k] * mul;
+        f.x *= s; f.y *= s;
+        const T rh = (T)f.x, ih = (T)f.y;
+        hv[2 * m] = rh;  hv[2 * m + 1] = ih;
+        lv[2 * m] = (T)(f.x - (float)rh);  lv[2 * m + 1] = (T)(f.y - (float)ih);
+      }
+      *reinterpret_cast<vec *>(dh + 8 * g) = hv;
+      *reinterpret_cast<vec *>(dl + 8 * g) = lv;
+    }
+  };
+
+  f32x16 accR[2][2], accI[2][2];
+  f32x16 runR[2][2], runI[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        accR[a][b][e] = 0.f; accI[a][b][e] = 0.f;
+        if (SCALED) { runR[a][b][e] = 0.f; runI[a][b][e] = 0.f; }
+      }
+
+  const int kq = lane >> 5, idx = lane & 31;
+  const int ar0 = wr * 64 + idx, bc0 = wc * 64 + idx;
+
+  load_chunk(0);
+  produce(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) load_chunk(ch + 1);
+#pragma unroll
+    for (int g = 0; g < KS / 8; ++g) {
+      const int ko = g * 16 + kq * 8;
+      const vec ah0 = *reinterpret_cast<const vec *>(&sAh[buf][ar0][ko]);
+      const vec ah1 = *reinterpret_cast<const vec *>(&sAh[buf][ar0 + 32][ko]);
+      const vec al0 = *reinterpret_cast<const vec *>(&sAl[buf][ar0][ko]);
+      const vec al1 = *reinterpret_cast<const vec *>(&sAl[buf][ar0 + 32][ko]);
+      const vec bh0 = *reinterpret_cast<const vec *>(&sBh[buf][bc0][ko]);
+      const vec bh1 = *reinterpret_cast<const vec *>(&sBh[buf][bc0 + 32][ko]);
+      const vec bl0 = *reinterpret_cast<const vec *>(&sBl[buf][bc0][ko]);
+      const vec bl1 = *reinterpret_cast<const vec *>(&sBl[buf][bc0 + 32][ko]);
+      const vec yh0 = rot_neg(bh0), yh1 = rot_neg(bh1), yl0 = rot_neg(bl0), yl1 = rot_neg(bl1);
+#define GW_SPLIT3(ACC, A_H, A_L, B_H, B_L)   \
+  ACC = SplitTraits<T>::mfma(A_H, B_H, ACC); \
+  ACC = SplitTraits<T>::mfma(A_H, B_L, ACC); \
+  ACC = SplitTraits<T>::mfma(A_L, B_H, ACC);
+      GW_SPLIT3(accR[0][0], ah0, al0, bh0, bl0)
+      GW_SPLIT3(accI[0][0], ah0, al0, yh0, yl0)
+      GW_SPLIT3(accR[0][1], ah0, al0, bh1, bl1)
+      GW_SPLIT3(accI[0][1], ah0, al0, yh1, yl1)
+      GW_SPLIT3(accR[1][0], ah1, al1, bh0, bl0)
+      GW_SPLIT3(accI[1][0], ah1, al1, yh0, yl0)
+      GW_SPLIT3(accR[1][1], ah1, al1, bh1, bl1)
+      GW_SPLIT3(accI[1][1], ah1, al1, yh1, yl1)
+#undef GW_SPLIT3
+    }
+    if (SCALED && (ch % nchc) == nchc - 1) {
+      // end of one occupied band: fold its partial sum back with 2^(-2 e_v)
+      const float back = ldexpf(1.0f, -2 * band_exp[ch / nchc]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          runR[a][b] += accR[a][b] * back;
+          runI[a][b] += accI[a][b] * back;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) { accR[a][b][e] = 0.f; accI[a][b][e] = 0.f; }
+        }
+    }
+    if (ch + 1 < nch) produce(buf ^ 1);
+    __syncthreads();
+  }
+  if (SCALED) store_tile(P, nr, I0, J0, bi != bj, accumulate, runR, runI, wr, wc, lane);
+  else store_tile(P, nr, I0, J0, bi != bj, accumulate, accR, accI, wr, wc, lane);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Per-band exponents of the FP16 path: e_v = floor(log2(2^14 / bound_v)) with
+// bound_v = max_r |psi_v(r)| * max_{c,r} |psi_c(r)| * max_c s_vc >= max |f_vc(r)|, so the
+// scaled f of band v stays below 2^14 (FP16 max 65504) and its lo part stays normal for
+// every entry within 2^-10 of the band's largest.
+// ---------------------------------------------------------------------------------------------
+__global__ void absmax_rows_kernel(const float2 *__restrict__ psi, int nrows, int nr, float *__restrict__ out) {
+  const int row = blockIdx.x;
+  float m = 0.f;
+  for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+    const float2 z = psi[(size_t)row * nr + r];
+    m = fmaxf(m, sqrtf(z.x * z.x + z.y * z.y));
+  }
+  __shared__ float red[256];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[row] = red[0];
+}
+
+__global__ void band_exponent_kernel(const float *__restrict__ vmax, int nv, const float *__restrict__ cmax, int nc,
+                                     const float *__restrict__ scale, int *__restrict__ band_exp) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  float cm = 0.f, sm = 0.f;
+  for (int c = 0; c < nc; ++c) { cm = fmaxf(cm, cmax[c]); sm = fmaxf(sm, scale[v * nc + c]); }
+  const float bound = vmax[v] * cm * sm;
+  int e = 0;
+  if (bound > 0.f) e = (int)floorf(log2f(16384.0f / bound));
+  band_exp[v] = max(-60, min(60, e));
+}
+
+hipError_t launch_band_exponents(const float2 *psi_v, int nv, const float2 *psi_c, int nc, int nr,
+                                 const float *scale, int *band_exp, hipStream_t s) {
+  // band_exp is followed in the same workspace by nv + nc floats of row maxima.
+  float *vmax = reinterpret_cast<float *>(band_exp + nv);
+  float *cmax = vmax + nv;
+  hipLaunchKernelGGL(absmax_rows_kernel, dim3(nv), dim3(256), 0, s, psi_v, nv, nr, vmax);
+  hipLaunchKernelGGL(absmax_rows_kernel, dim3(nc), dim3(256), 0, s, psi_c, nc, nr, cmax);
+  hipLaunchKernelGGL(band_exponent_kernel, dim3((nv + 63) / 64), dim3(64), 0, s, vmax, nv, cmax, nc, scale,
+                     band_exp);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Tile table and dispatch
+// ---------------------------------------------------------------------------------------------
+struct TileCfg { const char *name; int precision; };
+static const TileCfg kTiles[] = {
+  {"fp32_t128_fold", GW_FP32},
+  {"fp32_t128", GW_FP32},
+  {"bf16split_t128", GW_SPLIT_BF16},
+  {"fp16split_t128_scaled", GW_SPLIT_FP16_SCALED},
+};
+
+int herk_tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
+const char *herk_tile_name(int t) { return (t >= 0 && t < herk_tile_count()) ? kTiles[t].name : ""; }
+bool herk_tile_supports(int t, int precision) {
+  return t >= 0 && t < herk_tile_count() && kTiles[t].precision == precision;
+}
+int herk_default_tile(int precision, int nr) {
+  (void)nr;
+  switch (precision) {
+    case GW_FP32: return 0;
+    case GW_SPLIT_BF16: return 2;
+    case GW_SPLIT_FP16_SCALED: return 3;
+  }
+  return -1;
+}
+
+hipError_t launch_herk(int precision, int tile, const float2 *psi_v, const float2 *psi_c, const float *scale,
+                       const int *band_exp, float2 *p, int nr, int nv, int nc, int accumulate, hipStream_t s) {
+  if (tile < 0) tile = herk_default_tile(precision, nr);
+  const int nb = (nr + HB - 1) / HB;
+  const int ntiles = nb * (nb + 1) / 2;
+  dim3 grid(ntiles), block(NTHR);
+  switch (tile) {
+    case 0:
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_fp32_kernel<true>), grid, block, 0, s, psi_v, psi_c, scale, p, nr, nv,
+                         nc, ntiles, accumulate);
+      break;
+    case 1:
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_fp32_kernel<false>), grid, block, 0, s, psi_v, psi_c, scale, p, nr, nv,
+                         nc, ntiles, accumulate);
+      break;
+    case 2:
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_kernel<__bf16, false>), grid, block, 0, s, psi_v, psi_c, scale,
+                         band_exp, p, nr, nv, nc, ntiles, accumulate);
+      break;
+    case 3:
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_kernel<_Float16, true>), grid, block, 0, s, psi_v, psi_c, scale,
+                         band_exp, p, nr, nv, nc, ntiles, accumulate);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gwi

@@ -1,0 +1,219 @@
+"""GPU parity: every entry point of the C ABI against the FP64 oracle on the same seeded inputs.
+
+Inputs are the complex64-rounded orbitals the GPU receives (the oracle upcasts them), so the
+reported errors are those of the kernels.  Tolerances (relative Frobenius unless stated):
+FP32 path 1e-5 for P, P~ and eps^-1; split BF16 / FP16 1e-4."""
+import numpy as np
+import pytest
+
+import gwsynth as gs
+import oracle as orc
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def gw():
+    _need_gpu()
+    import paper_1810_07772_amd as gw
+    gw.load()
+    return gw
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def c64(x):
+    return dev(np.asarray(x).astype(np.complex64))
+
+
+def sys_c64(n, nv, nc, r2, seed=0, q=(0.0, 0.0, 0.0)):
+    s = gs.make_system(n, nv, nc, r2_psi=r2, seed=seed, q=q).as_c64()
+    print(f"[case] n={n} nv={nv} nc={nc} r2={r2} seed={seed} q={q} ng={s.ng}", flush=True)
+    return s
+
+
+# --- pair products --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,nv,nc,r2", [(12, 8, 64, 10.0), (5, 3, 7, 3.0)])
+def test_pair_products(gw, n, nv, nc, r2):
+    s = sys_c64(n, nv, nc, r2)
+    f = gw.pair_products(c64(s.psi_v), c64(s.psi_c), s.e_v, s.e_c, prefactor=2.0)
+    torch.cuda.synchronize()
+    ref = orc.pair_products(s.psi_v, s.psi_c, s.e_v, s.e_c, prefactor=2.0)
+    got = f.cpu().numpy()
+    err = np.abs(got - ref) / np.max(np.abs(ref))
+    assert err.max() < 2e-7, err.max()
+
+
+# --- P(r, r') --------------------------------------------------------------------------------
+@pytest.mark.parametrize("n,nv,nc,r2,tile", [
+    (12, 8, 64, 10.0, -1),        # 12^3 workload: several 128-tiles, exact chunk multiples
+    (10, 3, 37, 6.0, -1),         # ragged: nr = 1000 (not a tile multiple), nc not a chunk multiple
+    (12, 8, 64, 10.0, 1),         # the single-level FP32 tile
+    (4, 1, 1, 1.0, -1),           # degenerate: one pair, nr = 64 (one partial tile)
+])
+def test_polarizability_r_fp32(gw, n, nv, nc, r2, tile):
+    s = sys_c64(n, nv, nc, r2)
+    p = gw.polarizability_r(c64(s.psi_v), c64(s.psi_c), s.e_v, s.e_c, tile=tile)
+    torch.cuda.synchronize()
+    ref = orc.polarizability_r(s.psi_v, s.psi_c, s.e_v, s.e_c)
+    got = p.cpu().numpy()
+    e = orc.rel_f(got, ref)
+    print(f"rel_F(P) = {e:.3e}")
+    assert e < 1e-5
+    # Hermitian and negative semidefinite as written (both triangles)
+    assert np.max(np.abs(got - got.conj().T)) <= 1e-6 * np.max(np.abs(got))
+
+
+def test_polarizability_r_accumulate_and_prefactor(gw):
+    s = sys_c64(8, 6, 24, 6.0, seed=3)
+    pv, pc = c64(s.psi_v), c64(s.psi_c)
+    p = gw.polarizability_r(pv[:2].contiguous(), pc, s.e_v[:2], s.e_c, prefactor=2.0)
+    gw.polarizability_r(pv[2:].contiguous(), pc, s.e_v[2:], s.e_c, prefactor=2.0, accumulate=True, out=p)
+    torch.cuda.synchronize()
+    ref = orc.polarizability_r(s.psi_v, s.psi_c, s.e_v, s.e_c, prefactor=2.0)
+    assert orc.rel_f(p.cpu().numpy(), ref) < 1e-5
+
+
+# --- sphere transforms -------------------------------------------------------------------------
+@pytest.mark.parametrize("n,r2,q", [(12, 10.0, (0, 0, 0)), (8, 6.0, (0.1, -0.2, 0.05)), (6, 4.0, (0, 0, 0)),
+                                    (9, 9.0, (0.25, 0.0, 0.0)), (16, 30.0, (0, 0, 0)), (5, 1e9, (0, 0, 0))])
+def test_sphere_transform(gw, n, r2, q):
+    rng = np.random.default_rng(7)
+    nr = n ** 3
+    a = (rng.standard_normal((nr, nr)) + 1j * rng.standard_normal((nr, nr))).astype(np.complex64)
+    mill = gs.sphere((n, n, n), r2=r2, q=q)
+    print(f"[case] n={n} ng={len(mill)} q={q}", flush=True)
+    out = gw.sphere_transform(dev(a), (n, n, n), mill)
+    torch.cuda.synchronize()
+    ref = orc.to_sphere(a.astype(np.complex128), (n, n, n), mill)
+    e = orc.rel_f(out.cpu().numpy(), ref)
+    print(f"rel_F = {e:.3e}")
+    assert e < 2e-6
+
+
+# --- the whole build to P~ -----------------------------------------------------------------------
+@pytest.mark.parametrize("n,nv,nc,r2,q", [(12, 8, 64, 10.0, (0, 0, 0)), (8, 4, 20, 6.0, (0.0, 0.0, 0.001))])
+def test_polarizability_end_to_end(gw, n, nv, nc, r2, q):
+    s = sys_c64(n, nv, nc, r2, q=q)
+    prr = torch.empty((s.nr, s.nr), dtype=torch.complex64, device="cuda:0")
+    pgg = gw.polarizability(c64(s.psi_v), c64(s.psi_c), s.e_v, s.e_c, s.n, s.a_bohr, s.q, s.miller, p_rr=prr)
+    pgg2 = gw.polarizability(c64(s.psi_v), c64(s.psi_c), s.e_v, s.e_c, s.n, s.a_bohr, s.q, s.miller)  # internal P
+    torch.cuda.synchronize()
+    p_ref = orc.polarizability_r(s.psi_v, s.psi_c, s.e_v, s.e_c)
+    pt_ref = orc.to_sphere(p_ref, s.n, s.miller)
+    assert orc.rel_f(prr.cpu().numpy(), p_ref) < 1e-5
+    e = orc.rel_f(pgg.cpu().numpy(), pt_ref)
+    print(f"rel_F(P~) = {e:.3e}")
+    assert e < 1e-5
+    assert np.array_equal(pgg.cpu().numpy(), pgg2.cpu().numpy())
+
+
+# --- eps and eps^-1 ------------------------------------------------------------------------------
+def test_epsilon_build(gw):
+    s = sys_c64(8, 4, 24, 6.0, seed=5)
+    rng = np.random.default_rng(1)
+    pt = orc.to_sphere(orc.polarizability_r(s.psi_v, s.psi_c, s.e_v, s.e_c), s.n, s.miller)
+    pt32 = (pt + 1e-3 * np.abs(pt).max() * rng.standard_normal(pt.shape)).astype(np.complex64)  # not Hermitian
+    eps = gw.epsilon(dev(pt32), s.n, s.a_bohr, s.q, s.miller, head=1.7)
+    torch.cuda.synchronize()
+    h = 0.5 * (pt32.astype(np.complex128) + pt32.astype(np.complex128).conj().T)
+    ref = orc.epsilon(h, orc.coulomb_sqrt(s.n, s.a_bohr, s.q, s.miller), head=1.7)
+    got = eps.cpu().numpy()
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref))
+    assert got[0, 0] == 1.7
+
+
+@pytest.mark.parametrize("n", [1, 31, 32, 100, 257])
+def test_hpd_inverse(gw, n):
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    a = x @ x.conj().T / n + np.eye(n)
+    inv = gw.hpd_inverse(dev(a))
+    torch.cuda.synchronize()
+    ref = np.linalg.inv(a)
+    e = orc.rel_f(inv.cpu().numpy(), ref)
+    print(f"n={n} rel_F = {e:.3e}")
+    assert e < 1e-12
+
+
+def test_hpd_inverse_not_pd(gw):
+    n = 70
+    a = np.eye(n, dtype=np.complex128)
+    a[40, 40] = -1.0
+    with pytest.raises(gw.GwError) as ei:
+        gw.hpd_inverse(dev(a))
+    assert ei.value.status == 4 and "pivot 41" in str(ei.value)
+
+
+@pytest.mark.parametrize("q,head", [((0, 0, 0), 1.0), ((0.0, 0.0, 0.001), 1.0), ((0.2, 0.1, 0.05), 1.0)])
+def test_eps_inverse_end_to_end(gw, q, head):
+    s = sys_c64(12, 8, 64, 10.0, q=q)
+    pgg = gw.polarizability(c64(s.psi_v), c64(s.psi_c), s.e_v, s.e_c, s.n, s.a_bohr, s.q, s.miller)
+    einv = gw.eps_inverse(pgg, s.n, s.a_bohr, s.q, s.miller, head=head)
+    torch.cuda.synchronize()
+    pt_ref = orc.to_sphere(orc.polarizability_r(s.psi_v, s.psi_c, s.e_v, s.e_c), s.n, s.miller)
+    ref = orc.eps_inverse(orc.epsilon(pt_ref, orc.coulomb_sqrt(s.n, s.a_bohr, s.q, s.miller), head))
+    got = einv.cpu().numpy()
+    e = orc.rel_f(got, ref)
+    # eps^-1 - I: at tiny |q| the head row and column carry V(q) ~ 1/|q|^2 times the single-precision
+    # rounding of P~(0, .), which is conditioning of the input, so they are left out of this measure.
+    body = slice(1, None) if 0 < np.linalg.norm(q) < 1e-2 else slice(0, None)
+    eye = np.eye(len(ref))
+    e2 = orc.rel_f((got - eye)[body, body], (ref - eye)[body, body])
+    print(f"rel_F(eps^-1) = {e:.3e}, rel_F(eps^-1 - I) = {e2:.3e}")
+    assert e < 1e-5 and e2 < 1e-4
+
+
+# --- precision variants (workload 3: the 12^3 system, rows r = 0 mod 8 of P) -------------------------
+@pytest.mark.parametrize("prec,tol", [("bf16", 1e-4), ("fp16", 1e-4), ("fp32", 1e-5)])
+def test_precision_variants(gw, prec, tol):
+    s = sys_c64(12, 8, 64, 10.0)
+    prr = torch.empty((s.nr, s.nr), dtype=torch.complex64, device="cuda:0")
+    pgg = gw.polarizability(c64(s.psi_v), c64(s.psi_c), s.e_v, s.e_c, s.n, s.a_bohr, s.q, s.miller,
+                            precision=prec, p_rr=prr)
+    einv = gw.eps_inverse(pgg, s.n, s.a_bohr, s.q, s.miller)
+    torch.cuda.synchronize()
+    rows = np.arange(0, s.nr, 8)
+    p_full = orc.polarizability_r(s.psi_v, s.psi_c, s.e_v, s.e_c)
+    pt_ref = orc.to_sphere(p_full, s.n, s.miller)
+    ei_ref = orc.eps_inverse(orc.epsilon(pt_ref, orc.coulomb_sqrt(s.n, s.a_bohr, s.q, s.miller)))
+    ep = orc.rel_f(prr.cpu().numpy()[rows], p_full[rows])
+    ept = orc.rel_f(pgg.cpu().numpy(), pt_ref)
+    eei = orc.rel_f(einv.cpu().numpy(), ei_ref)
+    print(f"{prec}: rel_F P(rows)={ep:.3e} P~={ept:.3e} eps^-1={eei:.3e}")
+    assert ep < tol and ept < tol and eei < tol
+
+
+# --- errors and workspace --------------------------------------------------------------------------
+def test_invalid_arguments_raise(gw):
+    s = sys_c64(4, 2, 3, 2.0)
+    with pytest.raises(gw.GwError) as ei:
+        gw.polarizability_r(c64(s.psi_v), c64(s.psi_c), s.e_v, np.full(3, -1.0))
+    assert ei.value.status == 1
+    bad = s.miller.copy()
+    bad[1] = bad[0]
+    with pytest.raises(gw.GwError) as ei:
+        gw.sphere_transform(torch.zeros((64, 64), dtype=torch.complex64, device="cuda:0"), (4, 4, 4), bad)
+    assert ei.value.status == 1
+    with pytest.raises(gw.GwError) as ei:
+        gw.sphere_transform(torch.zeros((343, 343), dtype=torch.complex64, device="cuda:0"), (7, 7, 7),
+                            gs.sphere((7, 7, 7), r2=2.0))
+    assert ei.value.status == 5
+
+
+def test_workspace_cap(gw):
+    s = sys_c64(8, 2, 8, 4.0)
+    ctx = gw.Context(0, workspace_cap=1 << 16)
+    with pytest.raises(gw.GwError) as ei:
+        gw.polarizability(c64(s.psi_v), c64(s.psi_c), s.e_v, s.e_c, s.n, s.a_bohr, s.q, s.miller, ctx=ctx)
+    assert ei.value.status == 2
+    ctx.close()
