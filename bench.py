@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Benchmark of the static polarizability build on one MI355X.
+
+A step is one pass of the whole path over the 36^3 workload (N_r = 46656, Nv = 128, Nc = 1024,
+K = 131072, 4067-vector sphere, q = 0): the fused pair-product + Hermitian rank-K update into
+P(r,r') (17.4 GB complex64), both transforms to P~(g,g'), then eps and its FP64 inverse.  Inputs
+are seeded synthetic orbitals resident in HBM before timing starts.
+
+The headline value is the P-build rate (useful flops of the update + pair products, divided by
+the time of the update and the transforms) of the split-BF16 build; the FP32 build is measured
+in the same run for the comparison the metric asks for.  Prints one JSON line."""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "P-build TFLOP/s + % MFMA peak, FP32 vs split-BF16 at <=1e-4 rel err vs FP64"
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "fp64": 78.6}
+HBM_GBS = 8000.0
+WORKLOADS = {
+    "si36": dict(n=36, nv=128, nc=1024, r2=98.0),     # production size
+    "si12": dict(n=12, nv=8, nc=64, r2=10.0),         # small case
+}
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def herk_flops(nr, k):
+    return 4.0 * nr * (nr + 1) * k          # complex MAC = 8 flops over the lower triangle with diagonal
+
+
+def pair_flops(nr, k):
+    return 8.0 * k * nr
+
+
+def sphere_bytes(nr, ng):
+    # read P once, write and read P^, write P~ (complex64)
+    return 8.0 * (nr * nr + 2.0 * ng * nr + ng * ng)
+
+
+def parity_small(gw, torch, prec):
+    """The 12^3 workload at `prec` against the FP64 oracle (rows r = 0 mod 8 of P, full P~, eps^-1)."""
+    import gwsynth as gs
+    import oracle as orc
+    s = gs.make_system(12, 8, 64, r2_psi=10.0, seed=0).as_c64()
+    dev = torch.device("cuda:0")
+    pv = torch.from_numpy(s.psi_v.astype(np.complex64)).to(dev)
+    pc = torch.from_numpy(s.psi_c.astype(np.complex64)).to(dev)
+    prr = torch.empty((s.nr, s.nr), dtype=torch.complex64, device=dev)
+    pgg = gw.polarizability(pv, pc, s.e_v, s.e_c, s.n, s.a_bohr, s.q, s.miller, precision=prec, p_rr=prr)
+    einv = gw.eps_inverse(pgg, s.n, s.a_bohr, s.q, s.miller)
+    torch.cuda.synchronize()
+    rows = np.arange(0, s.nr, 8)
+    p = orc.polarizability_r(s.psi_v, s.psi_c, s.e_v, s.e_c)
+    pt = orc.to_sphere(p, s.n, s.miller)
+    ei = orc.eps_inverse(orc.epsilon(pt, orc.coulomb_sqrt(s.n, s.a_bohr, s.q, s.miller)))
+    return {"P_rows": orc.rel_f(prr.cpu().numpy()[rows], p[rows]), "P_gg": orc.rel_f(pgg.cpu().numpy(), pt),
+            "eps_inv": orc.rel_f(einv.cpu().numpy(), ei)}
+
+
+def cpu_baseline(sysd, rows, nv_sample):
+    """The FP64 oracle on a bounded sample of the same workload: `rows` rows of P(r,r') summed over
+    the first `nv_sample` occupied bands and every unoccupied band."""
+    import oracle as orc
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    pv = sysd["psi_v"][:nv_sample].astype(np.complex128)
+    pc = sysd["psi_c"].astype(np.complex128)
+    t0 = time.perf_counter()
+    orc.polarizability_r(pv, pc, sysd["e_v"][:nv_sample], sysd["e_c"], rows=rows)
+    dt = time.perf_counter() - t0
+    flops = 8.0 * len(rows) * pv.shape[1] * (nv_sample * pc.shape[0])
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{len(rows)} rows of P(r,r') over {nv_sample} of {sysd['psi_v'].shape[0]} occupied bands "
+                      f"x {pc.shape[0]} unoccupied (full rows, no triangle saving), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="si36", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"], help="headline precision")
+    ap.add_argument("--compare", default="fp32", help="comma list of other precisions to time ('' for none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--tile", type=int, default=-1)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this library has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    for k in ("RANK", "WORLD_SIZE"):
+        if int(os.environ.get(k, "0" if k == "RANK" else "1")) != (0 if k == "RANK" else 1):
+            print("bench.py runs as a single process on one GPU.", file=sys.stderr)
+            sys.exit(2)
+
+    import torch
+    import gwsynth as gs
+    import paper_1810_07772_amd as gw
+    gw.load()
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    wl = WORKLOADS[args.workload]
+    log(f"generating workload {args.workload} {wl}")
+    s = gs.make_system(wl["n"], wl["nv"], wl["nc"], r2_psi=wl["r2"], seed=0)
+    nr, nv, nc, ng = s.nr, s.nv, s.nc, s.ng
+    K = nv * nc
+    psi_v64, psi_c64 = s.psi_v.astype(np.complex64), s.psi_c.astype(np.complex64)
+    pv = torch.from_numpy(psi_v64).to(dev)
+    pc = torch.from_numpy(psi_c64).to(dev)
+    prr = torch.empty((nr, nr), dtype=torch.complex64, device=dev)
+    pgg = torch.empty((ng, ng), dtype=torch.complex64, device=dev)
+    einv = torch.empty((ng, ng), dtype=torch.complex128, device=dev)
+    torch.cuda.synchronize()
+    log(f"inputs resident: nr={nr} nv={nv} nc={nc} K={K} ng={ng}; P is {nr * nr * 8 / 1e9:.2f} GB")
+
+    stream = torch.cuda.current_stream(dev)
+
+    def run(prec, steps, warmup):
+        def one(ev=None):
+            if ev:
+                ev[0].record(stream)
+            gw.polarizability_r(pv, pc, s.e_v, s.e_c, precision=prec, tile=args.tile if prec == args.precision else -1,
+                                out=prr)
+            if ev:
+                ev[1].record(stream)
+            gw.sphere_transform(prr, s.n, s.miller, out=pgg)
+            if ev:
+                ev[2].record(stream)
+            gw.eps_inverse(pgg, s.n, s.a_bohr, s.q, s.miller, out=einv)
+            if ev:
+                ev[3].record(stream)
+        for i in range(warmup):
+            t0 = time.perf_counter()
+            one()
+            torch.cuda.synchronize()
+            log(f"{prec}: warmup step {i + 1}/{warmup} {time.perf_counter() - t0:.2f} s")
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            one(evs[i])
+            log(f"{prec}: step {i + 1}/{steps} queued/done")
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        herk = np.mean([e[0].elapsed_time(e[1]) for e in evs]) / 1e3
+        fft = np.mean([e[1].elapsed_time(e[2]) for e in evs]) / 1e3
+        inv = np.mean([e[2].elapsed_time(e[3]) for e in evs]) / 1e3
+        pbuild = herk + fft
+        res = {
+            "precision": prec, "step_s": wall, "herk_s": herk, "transforms_s": fft, "eps_inverse_s": inv,
+            "pbuild_tflops": (herk_flops(nr, K) + pair_flops(nr, K)) / pbuild / 1e12,
+            "herk_tflops": herk_flops(nr, K) / herk / 1e12,
+            "transforms_gbs": sphere_bytes(nr, ng) / fft / 1e9,
+        }
+        peak = PEAK_TFLOPS["fp32" if prec == "fp32" else prec]
+        res["herk_frac_peak"] = res["herk_tflops"] / peak
+        if prec != "fp32":
+            res["herk_executed_frac_peak"] = 3.0 * res["herk_tflops"] / peak   # three MFMA products per pair
+        log(f"{prec}: step {wall:.3f} s, HERK {herk:.3f} s ({res['herk_tflops']:.1f} TFLOP/s, "
+            f"{100 * res['herk_frac_peak']:.1f}% of {peak} peak), transforms {fft * 1e3:.1f} ms, eps^-1 {inv * 1e3:.1f} ms")
+        return res
+
+    results = {}
+    compare = [p for p in args.compare.split(",") if p and p != args.precision]
+    for prec in compare + [args.precision]:
+        results[prec] = run(prec, args.steps, args.warmup)
+    head = results[args.precision]
+
+    parity = {}
+    if not args.no_parity:
+        for prec in [args.precision] + compare:
+            parity[prec] = parity_small(gw, torch, prec)
+            log(f"parity 12^3 {prec}: {parity[prec]}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(0)
+        rows = np.sort(rng.choice(nr, size=8, replace=False))
+        nv_sample = min(nv, 96)
+        log(f"cpu baseline: oracle on {len(rows)} rows x {nv_sample} occupied bands")
+        cpu = cpu_baseline({"psi_v": psi_v64, "psi_c": psi_c64, "e_v": s.e_v, "e_c": s.e_c}, rows, nv_sample)
+        log(f"cpu baseline: {cpu}")
+
+    peak = PEAK_TFLOPS["fp32" if args.precision == "fp32" else args.precision]
+    out = {
+        "metric": METRIC,
+        "value": round(head["pbuild_tflops"], 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["step_s"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"bf16": "bf16x3-split/fp32-acc", "fp16": "fp16x3-split-scaled/fp32-acc",
+                  "fp32": "fp32"}[args.precision],
+        "data": "synthetic (seeded random plane-wave orbitals, QR-orthonormalised; see DESIGN.md)",
+        "config": {"workload": f"{args.workload}: {wl['n']}^3 grid (N_r={nr}), Nv={nv}, Nc={nc}, K={K}, "
+                               f"N_g={ng}, q=0, P(r,r') complex64 {nr * nr * 8 / 1e9:.1f} GB",
+                   "precision": args.precision, "tile": args.tile},
+        "roofline": {"bound": "mfma", "achieved": round(head["herk_tflops"], 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(head["herk_frac_peak"], 4), "traffic": None,
+                     "kernel": f"herk ({args.precision})"},
+        "cpu_baseline": cpu,
+        "precisions": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                       for k, v in results.items()},
+        "speedup_vs_fp32": (round(results["fp32"]["pbuild_tflops"] and head["pbuild_tflops"] /
+                                  results["fp32"]["pbuild_tflops"], 3) if "fp32" in results else None),
+        "parity_12cubed_relF": parity,
+        "transforms_roofline": {"bound": "hbm", "achieved": round(head["transforms_gbs"], 1), "peak": HBM_GBS,
+                                "unit": "GB/s", "frac": round(head["transforms_gbs"] / HBM_GBS, 4)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
