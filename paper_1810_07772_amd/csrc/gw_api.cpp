@@ -253,12 +253,13 @@ int sphere_transform_impl(gw_ctx *ctx, const float2 *p_rr, gw_grid g, const int 
 int upload_scales(gw_ctx *ctx, const double *e_v, int nv, const double *e_c, int nc, double prefactor, float **scale,
                   hipStream_t s) {
   void *eb, *sb;
+  const int ldsc = scale_ld(nc);
   GW_STATUS(ws_get(ctx, WS_ENERGY, (size_t)(nv + nc) * sizeof(double), &eb, s));
-  GW_STATUS(ws_get(ctx, WS_SCALE, (size_t)nv * nc * sizeof(float), &sb, s));
+  GW_STATUS(ws_get(ctx, WS_SCALE, (size_t)nv * ldsc * sizeof(float), &sb, s));
   double *de = (double *)eb;
   GW_HIP(ctx, hipMemcpyAsync(de, e_v, nv * sizeof(double), hipMemcpyHostToDevice, s));
   GW_HIP(ctx, hipMemcpyAsync(de + nv, e_c, nc * sizeof(double), hipMemcpyHostToDevice, s));
-  GW_HIP(ctx, launch_scale_table(de, nv, de + nv, nc, prefactor, (float *)sb, s));
+  GW_HIP(ctx, launch_scale_table(de, nv, de + nv, nc, prefactor, (float *)sb, ldsc, s));
   *scale = (float *)sb;
   return GW_OK;
 }
@@ -272,9 +273,9 @@ int polarizability_r_impl(gw_ctx *ctx, const float2 *psi_v, int nv, const float2
     void *b;
     GW_STATUS(ws_get(ctx, WS_BSCALE, (size_t)(nv + nv + nc) * sizeof(int), &b, s));
     bexp = (int *)b;
-    GW_HIP(ctx, launch_band_exponents(psi_v, nv, psi_c, nc, nr, scale, bexp, s));
+    GW_HIP(ctx, launch_band_exponents(psi_v, nv, psi_c, nc, nr, scale, scale_ld(nc), bexp, s));
   }
-  GW_HIP(ctx, launch_herk(o.precision, o.tile, psi_v, psi_c, scale, bexp, p_rr, nr, nv, nc, o.accumulate, s));
+  GW_HIP(ctx, launch_herk(o.precision, o.tile, psi_v, psi_c, scale, scale_ld(nc), bexp, p_rr, nr, nv, nc, o.accumulate, s));
   return GW_OK;
 }
 
@@ -402,7 +403,8 @@ int gw_pair_products(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *psi
   hipStream_t s = as_stream(stream);
   float *scale = nullptr;
   GW_STATUS(upload_scales(ctx, e_v, nv, e_c, nc, prefactor, &scale, s));
-  GW_HIP(ctx, launch_pair_products((const float2 *)psi_v, nv, (const float2 *)psi_c, nc, nr, scale, (float2 *)f_out, s));
+  GW_HIP(ctx, launch_pair_products((const float2 *)psi_v, nv, (const float2 *)psi_c, nc, nr, scale, scale_ld(nc),
+                                   (float2 *)f_out, s));
   return GW_OK;
 }
 

@@ -43,10 +43,12 @@ enum SlotId {
 };
 
 // Kernel launchers.  All return hipSuccess or the launch error; all run on `s`.
+// Pair scales s_vc = sqrt(p / (E_c - E_v)) as float [nv][ldsc], zero for nc <= c < ldsc.
+int scale_ld(int nc);
 hipError_t launch_scale_table(const double *e_v, int nv, const double *e_c, int nc, double prefactor,
-                              float *scale, hipStream_t s);
+                              float *scale, int ldsc, hipStream_t s);
 hipError_t launch_pair_products(const float2 *psi_v, int nv, const float2 *psi_c, int nc, int nr,
-                                const float *scale, float2 *f, hipStream_t s);
+                                const float *scale, int ldsc, float2 *f, hipStream_t s);
 
 // Rank-K update P = -F^H F with the pair products formed in-kernel.
 // precision: enum gw_precision; tile: index into the tile table (-1 default).
@@ -54,10 +56,10 @@ int herk_tile_count();
 const char *herk_tile_name(int tile);
 bool herk_tile_supports(int tile, int precision);
 int herk_default_tile(int precision, int nr);
-hipError_t launch_herk(int precision, int tile, const float2 *psi_v, const float2 *psi_c, const float *scale,
+hipError_t launch_herk(int precision, int tile, const float2 *psi_v, const float2 *psi_c, const float *scale, int ldsc,
                        const int *band_exp, float2 *p, int nr, int nv, int nc, int accumulate, hipStream_t s);
 hipError_t launch_band_exponents(const float2 *psi_v, int nv, const float2 *psi_c, int nc, int nr,
-                                 const float *scale, int *band_exp, hipStream_t s);
+                                 const float *scale, int ldsc, int *band_exp, hipStream_t s);
 
 // FFT helpers.
 bool fft_size_supported(int n);

@@ -88,10 +88,10 @@ __device__ __forceinline__ void store_tile(float2 *__restrict__ P, int nr, int I
 // ---------------------------------------------------------------------------------------------
 constexpr int KC32 = 16;   // unoccupied bands per stage
 
-template <bool FOLD>
+template <bool FOLD, bool COUTER>
 __global__ __launch_bounds__(NTHR, 1) void herk_fp32_kernel(const float2 *__restrict__ psi_v,
                                                              const float2 *__restrict__ psi_c,
-                                                             const float *__restrict__ scale,
+                                                             const float *__restrict__ scale, int ldsc,
                                                              float2 *__restrict__ P, int nr, int nv, int nc,
                                                              int ntiles, int accumulate) {
   // [buf][pair][component][point]; A: f on the tile's rows, B: f on its columns, Y: (im, -re) of B.
@@ -116,9 +116,12 @@ __global__ __launch_bounds__(NTHR, 1) void herk_fp32_kernel(const float2 *__rest
   float2 cI[4][2], cJ[4][2];        // psi_c of the staged chunk
   float sc[4];
 
+  // Stage ch covers occupied band v and unoccupied bands c0 .. c0+KC32-1.  With COUTER the
+  // unoccupied chunk is the outer index and v the inner one, so the psi_c chunk stays in
+  // registers for nv consecutive stages and only psi_v (one value per point) is loaded per stage.
   auto load_chunk = [&](int ch) {
-    const int v = ch / nchc;
-    const int c0 = (ch - v * nchc) * KC32;
+    const int v = COUTER ? ch % nv : ch / nchc;
+    const int c0 = (COUTER ? ch / nv : ch % nchc) * KC32;
     const float2 z = make_float2(0.f, 0.f);
     const float2 *pv = psi_v + (size_t)v * nr;
     vI[0] = oki0 ? pv[ri] : z;  vI[1] = oki1 ? pv[ri + 1] : z;
@@ -127,10 +130,12 @@ __global__ __launch_bounds__(NTHR, 1) void herk_fp32_kernel(const float2 *__rest
     for (int i = 0; i < 4; ++i) {
       const int c = c0 + prow + 4 * i;
       const bool okc = c < nc;
-      sc[i] = okc ? scale[v * nc + c] : 0.f;
-      const float2 *pc = psi_c + (size_t)(okc ? c : 0) * nr;
-      cI[i][0] = (okc && oki0) ? pc[ri] : z;  cI[i][1] = (okc && oki1) ? pc[ri + 1] : z;
-      cJ[i][0] = (okc && okj0) ? pc[rj] : z;  cJ[i][1] = (okc && okj1) ? pc[rj + 1] : z;
+      sc[i] = okc ? scale[v * ldsc + c] : 0.f;
+      if (!COUTER || v == 0) {
+        const float2 *pc = psi_c + (size_t)(okc ? c : 0) * nr;
+        cI[i][0] = (okc && oki0) ? pc[ri] : z;  cI[i][1] = (okc && oki1) ? pc[ri + 1] : z;
+        cJ[i][0] = (okc && okj0) ? pc[rj] : z;  cJ[i][1] = (okc && okj1) ? pc[rj + 1] : z;
+      }
     }
   };
   auto produce = [&](int buf) {
@@ -183,7 +188,9 @@ __global__ __launch_bounds__(NTHR, 1) void herk_fp32_kernel(const float2 *__rest
       accR[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, x1, accR[1][1], 0, 0, 0);
       accI[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, y1, accI[1][1], 0, 0, 0);
     }
-    if (FOLD && ((ch % nchc) == nchc - 1)) {
+    // two-level sum: fold after each block of the K loop (one occupied band, or one
+    // unoccupied chunk over all occupied bands with COUTER)
+    if (FOLD && (COUTER ? (ch % nv) == nv - 1 : (ch % nchc) == nchc - 1)) {
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -242,10 +249,10 @@ __device__ __forceinline__ V rot_neg(V b) {
   return __builtin_bit_cast(V, y);
 }
 
-template <typename T, bool SCALED>
+template <typename T, bool SCALED, bool COUTER>
 __global__ __launch_bounds__(NTHR, 1) void herk_split_kernel(const float2 *__restrict__ psi_v,
                                                               const float2 *__restrict__ psi_c,
-                                                              const float *__restrict__ scale,
+                                                              const float *__restrict__ scale, int ldsc,
                                                               const int *__restrict__ band_exp,
                                                               float2 *__restrict__ P, int nr, int nv, int nc,
                                                               int ntiles, int accumulate) {
@@ -276,9 +283,10 @@ __global__ __launch_bounds__(NTHR, 1) void herk_split_kernel(const float2 *__res
   float sc[KS];
   float mul = 1.0f;
 
+  static_assert(!(SCALED && COUTER), "the per-band scale needs the occupied band as the outer K index");
   auto load_chunk = [&](int ch) {
-    const int v = ch / nchc;
-    const int c0 = (ch - v * nchc) * KS;
+    const int v = COUTER ? ch % nv : ch / nchc;
+    const int c0 = (COUTER ? ch / nv : ch % nchc) * KS;
     const float2 z = make_float2(0.f, 0.f);
     pvv = okp ? psi_v[(size_t)v * nr + gpt] : z;
     if (SCALED) mul = ldexpf(1.0f, band_exp[v]);
@@ -286,8 +294,8 @@ __global__ __launch_bounds__(NTHR, 1) void herk_split_kernel(const float2 *__res
     for (int k = 0; k < KS; ++k) {
       const int c = c0 + k;
       const bool okc = c < nc;
-      sc[k] = okc ? scale[v * nc + c] : 0.f;
-      pc[k] = (okc && okp) ? psi_c[(size_t)c * nr + gpt] : z;
+      sc[k] = okc ? scale[v * ldsc + c] : 0.f;
+      if (!COUTER || v == 0) pc[k] = (okc && okp) ? psi_c[(size_t)c * nr + gpt] : z;
     }
   };
   auto produce = [&](int buf) {
@@ -379,6 +387,159 @@ __global__ __launch_bounds__(NTHR, 1) void herk_split_kernel(const float2 *__res
 }
 
 // ---------------------------------------------------------------------------------------------
+// Wave-specialised split kernel: 8 waves per workgroup.  Waves 0-3 only issue MFMAs (each owns a
+// 64x64 quadrant of the 128x128 tile); waves 4-7 only form pair products, split them and stage
+// them in LDS for the next stage.  Each SIMD then holds one MFMA wave and one producer wave, so
+// the producer's VALU work runs while the matrix core executes the other wave's MFMAs.  K order:
+// unoccupied chunk outer, occupied band inner (the psi_c chunk of a producer thread stays in
+// registers for nv stages).  Loads are branch-free: indices are clamped and the value masked.
+// ---------------------------------------------------------------------------------------------
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// (a, b) -> one word holding (bf16 RNE(a), bf16 RNE(b)); gfx950 does this in one instruction.
+__device__ __forceinline__ unsigned pk_bf16(float a, float b) {
+  const f32x2 v = {a, b};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+}
+
+__global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2 *__restrict__ psi_v,
+                                                                     const float2 *__restrict__ psi_c,
+                                                                     const float *__restrict__ scale, int ldsc,
+                                                                     float2 *__restrict__ P, int nr, int nv, int nc,
+                                                                     int ntiles, int accumulate) {
+  typedef bf16x8 vec;
+  __shared__ __attribute__((aligned(16))) __bf16 sAh[2][HB][SROW];
+  __shared__ __attribute__((aligned(16))) __bf16 sAl[2][HB][SROW];
+  __shared__ __attribute__((aligned(16))) __bf16 sBh[2][HB][SROW];
+  __shared__ __attribute__((aligned(16))) __bf16 sBl[2][HB][SROW];
+
+  int bi, bj;
+  tile_of(xcd_remap(blockIdx.x, ntiles), bi, bj);
+  const int I0 = bi * HB, J0 = bj * HB;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform role
+  const int nchc = (nc + KS - 1) / KS;
+  const int nch = nv * nchc;
+  const bool producer = wave >= 4;
+
+  // ---- producer state: one grid point of the rows (waves 4, 6) or columns (waves 5, 7)
+  const int pw = wave - 4;
+  const int pside = pw & 1;
+  const int ppt = lane + 64 * (pw >> 1);
+  // Loads need no masks: the scale table is zero for unoccupied bands past nc (so those pair
+  // products vanish), and a point past nr only feeds output entries that are never stored, so
+  // out-of-range indices are clamped to valid addresses.
+  const int gpt = min((pside ? J0 : I0) + ppt, nr - 1);
+  float2 pc[KS], pcn[KS];
+  float2 pvv;
+  float sc[KS];
+
+  auto load_c = [&](float2 (&dst)[KS], int cc) {   // psi_c of chunk cc at this thread's point
+#pragma unroll
+    for (int k = 0; k < KS; ++k) dst[k] = psi_c[(size_t)min(cc * KS + k, nc - 1) * nr + gpt];
+  };
+  auto load_v = [&](int ch) {                       // psi_v and the scales of stage ch
+    const int v = ch % nv, c0 = (ch / nv) * KS;
+    pvv = psi_v[(size_t)v * nr + gpt];
+    const float *srow = scale + (size_t)v * ldsc + c0;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) sc[k] = srow[k];
+  };
+  auto produce = [&](int buf) {
+    u32x4 *dh = reinterpret_cast<u32x4 *>(pside ? &sBh[buf][ppt][0] : &sAh[buf][ppt][0]);
+    u32x4 *dl = reinterpret_cast<u32x4 *>(pside ? &sBl[buf][ppt][0] : &sAl[buf][ppt][0]);
+#pragma unroll
+    for (int g = 0; g < KS / 4; ++g) {
+      u32x4 hv, lv;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int k = 4 * g + m;
+        const float fx = (pvv.x * pc[k].x + pvv.y * pc[k].y) * sc[k];
+        const float fy = (pvv.x * pc[k].y - pvv.y * pc[k].x) * sc[k];
+        const unsigned w = pk_bf16(fx, fy);
+        hv[m] = w;
+        lv[m] = pk_bf16(fx - __builtin_bit_cast(float, w << 16), fy - __builtin_bit_cast(float, w & 0xffff0000u));
+      }
+      dh[g] = hv;
+      dl[g] = lv;
+    }
+  };
+
+  // The two roles run separate loops (each wave takes one of them as a whole), so the
+  // producer's registers and the consumer's accumulators are never live at the same time.
+  // Both loops pass the same number of workgroup barriers.
+  if (producer) {
+    load_c(pc, 0);
+    load_v(0);
+    produce(0);
+    if (nch > 1) load_v(1);
+    if (nv == 1 && nch > 1) load_c(pcn, 1);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+      if (ch + 1 < nch) {
+        if ((ch + 1) % nv == 0) {                          // stage ch+1 opens the next unoccupied chunk
+#pragma unroll
+          for (int k = 0; k < KS; ++k) pc[k] = pcn[k];
+        }
+        produce((ch & 1) ^ 1);
+        if (ch + 2 < nch) {
+          load_v(ch + 2);                                  // in flight until the next stage
+          if ((ch + 2) % nv == 0) load_c(pcn, (ch + 2) / nv);
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+
+  // ---- consumer
+  const int wr = (wave & 3) >> 1, wc = wave & 1;
+  const int kq = lane >> 5, idx = lane & 31;
+  const int ar0 = wr * 64 + idx, bc0 = wc * 64 + idx;
+  f32x16 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) { accR[a][b][e] = 0.f; accI[a][b][e] = 0.f; }
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+#pragma unroll
+    for (int g = 0; g < KS / 8; ++g) {
+      const int ko = g * 16 + kq * 8;
+      const vec ah0 = *reinterpret_cast<const vec *>(&sAh[buf][ar0][ko]);
+      const vec ah1 = *reinterpret_cast<const vec *>(&sAh[buf][ar0 + 32][ko]);
+      const vec al0 = *reinterpret_cast<const vec *>(&sAl[buf][ar0][ko]);
+      const vec al1 = *reinterpret_cast<const vec *>(&sAl[buf][ar0 + 32][ko]);
+      const vec bh0 = *reinterpret_cast<const vec *>(&sBh[buf][bc0][ko]);
+      const vec bh1 = *reinterpret_cast<const vec *>(&sBh[buf][bc0 + 32][ko]);
+      const vec bl0 = *reinterpret_cast<const vec *>(&sBl[buf][bc0][ko]);
+      const vec bl1 = *reinterpret_cast<const vec *>(&sBl[buf][bc0 + 32][ko]);
+      const vec yh0 = rot_neg(bh0), yh1 = rot_neg(bh1), yl0 = rot_neg(bl0), yl1 = rot_neg(bl1);
+      // eight independent accumulators per product, so consecutive MFMAs never chain
+#define GW_PROD8(A0, A1, B0, B1, Y0, Y1)                                          \
+  accR[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, B0, accR[0][0], 0, 0, 0); \
+  accI[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, Y0, accI[0][0], 0, 0, 0); \
+  accR[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, B1, accR[0][1], 0, 0, 0); \
+  accI[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, Y1, accI[0][1], 0, 0, 0); \
+  accR[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B0, accR[1][0], 0, 0, 0); \
+  accI[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, Y0, accI[1][0], 0, 0, 0); \
+  accR[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B1, accR[1][1], 0, 0, 0); \
+  accI[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, Y1, accI[1][1], 0, 0, 0);
+      GW_PROD8(ah0, ah1, bh0, bh1, yh0, yh1)     // hi * hi
+      GW_PROD8(ah0, ah1, bl0, bl1, yl0, yl1)     // hi * lo
+      GW_PROD8(al0, al1, bh0, bh1, yh0, yh1)     // lo * hi
+#undef GW_PROD8
+    }
+    __syncthreads();
+  }
+  store_tile(P, nr, I0, J0, bi != bj, accumulate, accR, accI, wr, wc, lane);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Per-band exponents of the FP16 path: e_v = floor(log2(2^14 / bound_v)) with
 // bound_v = max_r |psi_v(r)| * max_{c,r} |psi_c(r)| * max_c s_vc >= max |f_vc(r)|, so the
 // scaled f of band v stays below 2^14 (FP16 max 65504) and its lo part stays normal for
@@ -402,11 +563,11 @@ __global__ void absmax_rows_kernel(const float2 *__restrict__ psi, int nrows, in
 }
 
 __global__ void band_exponent_kernel(const float *__restrict__ vmax, int nv, const float *__restrict__ cmax, int nc,
-                                     const float *__restrict__ scale, int *__restrict__ band_exp) {
+                                     const float *__restrict__ scale, int ldsc, int *__restrict__ band_exp) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nv) return;
   float cm = 0.f, sm = 0.f;
-  for (int c = 0; c < nc; ++c) { cm = fmaxf(cm, cmax[c]); sm = fmaxf(sm, scale[v * nc + c]); }
+  for (int c = 0; c < nc; ++c) { cm = fmaxf(cm, cmax[c]); sm = fmaxf(sm, scale[v * ldsc + c]); }
   const float bound = vmax[v] * cm * sm;
   int e = 0;
   if (bound > 0.f) e = (int)floorf(log2f(16384.0f / bound));
@@ -414,13 +575,13 @@ __global__ void band_exponent_kernel(const float *__restrict__ vmax, int nv, con
 }
 
 hipError_t launch_band_exponents(const float2 *psi_v, int nv, const float2 *psi_c, int nc, int nr,
-                                 const float *scale, int *band_exp, hipStream_t s) {
+                                 const float *scale, int ldsc, int *band_exp, hipStream_t s) {
   // band_exp is followed in the same workspace by nv + nc floats of row maxima.
   float *vmax = reinterpret_cast<float *>(band_exp + nv);
   float *cmax = vmax + nv;
   hipLaunchKernelGGL(absmax_rows_kernel, dim3(nv), dim3(256), 0, s, psi_v, nv, nr, vmax);
   hipLaunchKernelGGL(absmax_rows_kernel, dim3(nc), dim3(256), 0, s, psi_c, nc, nr, cmax);
-  hipLaunchKernelGGL(band_exponent_kernel, dim3((nv + 63) / 64), dim3(64), 0, s, vmax, nv, cmax, nc, scale,
+  hipLaunchKernelGGL(band_exponent_kernel, dim3((nv + 63) / 64), dim3(64), 0, s, vmax, nv, cmax, nc, scale, ldsc,
                      band_exp);
   return hipGetLastError();
 }
@@ -430,10 +591,13 @@ hipError_t launch_band_exponents(const float2 *psi_v, int nv, const float2 *psi_
 // ---------------------------------------------------------------------------------------------
 struct TileCfg { const char *name; int precision; };
 static const TileCfg kTiles[] = {
-  {"fp32_t128_fold", GW_FP32},
-  {"fp32_t128", GW_FP32},
-  {"bf16split_t128", GW_SPLIT_BF16},
-  {"fp16split_t128_scaled", GW_SPLIT_FP16_SCALED},
+  {"fp32_t128_fold_vouter", GW_FP32},
+  {"fp32_t128_vouter", GW_FP32},
+  {"bf16split_t128_vouter", GW_SPLIT_BF16},
+  {"fp16split_t128_scaled_vouter", GW_SPLIT_FP16_SCALED},
+  {"fp32_t128_fold_couter", GW_FP32},
+  {"bf16split_t128_couter", GW_SPLIT_BF16},
+  {"bf16split_t128_ws", GW_SPLIT_BF16},
 };
 
 int herk_tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -444,39 +608,39 @@ bool herk_tile_supports(int t, int precision) {
 int herk_default_tile(int precision, int nr) {
   (void)nr;
   switch (precision) {
-    case GW_FP32: return 0;
-    case GW_SPLIT_BF16: return 2;
+    case GW_FP32: return 4;
+    case GW_SPLIT_BF16: return 6;
     case GW_SPLIT_FP16_SCALED: return 3;
   }
   return -1;
 }
 
-hipError_t launch_herk(int precision, int tile, const float2 *psi_v, const float2 *psi_c, const float *scale,
+hipError_t launch_herk(int precision, int tile, const float2 *psi_v, const float2 *psi_c, const float *scale, int ldsc,
                        const int *band_exp, float2 *p, int nr, int nv, int nc, int accumulate, hipStream_t s) {
   if (tile < 0) tile = herk_default_tile(precision, nr);
   const int nb = (nr + HB - 1) / HB;
   const int ntiles = nb * (nb + 1) / 2;
   dim3 grid(ntiles), block(NTHR);
+#define GW_LAUNCH(KERNEL, ...) \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL), grid, block, 0, s, __VA_ARGS__)
   switch (tile) {
-    case 0:
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_fp32_kernel<true>), grid, block, 0, s, psi_v, psi_c, scale, p, nr, nv,
-                         nc, ntiles, accumulate);
-      break;
-    case 1:
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_fp32_kernel<false>), grid, block, 0, s, psi_v, psi_c, scale, p, nr, nv,
-                         nc, ntiles, accumulate);
-      break;
-    case 2:
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_kernel<__bf16, false>), grid, block, 0, s, psi_v, psi_c, scale,
-                         band_exp, p, nr, nv, nc, ntiles, accumulate);
-      break;
-    case 3:
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_kernel<_Float16, true>), grid, block, 0, s, psi_v, psi_c, scale,
-                         band_exp, p, nr, nv, nc, ntiles, accumulate);
+    case 0: GW_LAUNCH((herk_fp32_kernel<true, false>), psi_v, psi_c, scale, ldsc, p, nr, nv, nc, ntiles, accumulate); break;
+    case 1: GW_LAUNCH((herk_fp32_kernel<false, false>), psi_v, psi_c, scale, ldsc, p, nr, nv, nc, ntiles, accumulate); break;
+    case 2: GW_LAUNCH((herk_split_kernel<__bf16, false, false>), psi_v, psi_c, scale, ldsc, band_exp, p, nr, nv, nc, ntiles,
+                      accumulate); break;
+    case 3: GW_LAUNCH((herk_split_kernel<_Float16, true, false>), psi_v, psi_c, scale, ldsc, band_exp, p, nr, nv, nc, ntiles,
+                      accumulate); break;
+    case 4: GW_LAUNCH((herk_fp32_kernel<true, true>), psi_v, psi_c, scale, ldsc, p, nr, nv, nc, ntiles, accumulate); break;
+    case 5: GW_LAUNCH((herk_split_kernel<__bf16, false, true>), psi_v, psi_c, scale, ldsc, band_exp, p, nr, nv, nc, ntiles,
+                      accumulate); break;
+    case 6:
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_ws_kernel), grid, dim3(2 * NTHR), 0, s, psi_v, psi_c, scale,
+                         ldsc, p, nr, nv, nc, ntiles, accumulate);
       break;
     default:
       return hipErrorInvalidValue;
   }
+#undef GW_LAUNCH
   return hipGetLastError();
 }
 

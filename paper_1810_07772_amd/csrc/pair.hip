@@ -10,18 +10,21 @@
 
 namespace gwi {
 
+int scale_ld(int nc) { return (nc + 31) / 32 * 32; }
+
 __global__ void scale_table_kernel(const double *__restrict__ e_v, int nv, const double *__restrict__ e_c, int nc,
-                                   double prefactor, float *__restrict__ scale) {
+                                   double prefactor, float *__restrict__ scale, int ldsc) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nv * nc) return;
-  const int v = idx / nc, c = idx - v * nc;
-  scale[idx] = (float)sqrt(prefactor / (e_c[c] - e_v[v]));
+  if (idx >= nv * ldsc) return;
+  const int v = idx / ldsc, c = idx - v * ldsc;
+  scale[idx] = c < nc ? (float)sqrt(prefactor / (e_c[c] - e_v[v])) : 0.0f;
 }
 
 hipError_t launch_scale_table(const double *e_v, int nv, const double *e_c, int nc, double prefactor, float *scale,
-                              hipStream_t s) {
-  const int n = nv * nc;
-  hipLaunchKernelGGL(scale_table_kernel, dim3((n + 255) / 256), dim3(256), 0, s, e_v, nv, e_c, nc, prefactor, scale);
+                              int ldsc, hipStream_t s) {
+  const int n = nv * ldsc;
+  hipLaunchKernelGGL(scale_table_kernel, dim3((n + 255) / 256), dim3(256), 0, s, e_v, nv, e_c, nc, prefactor, scale,
+                     ldsc);
   return hipGetLastError();
 }
 
@@ -37,7 +40,7 @@ __device__ __forceinline__ float2 conj_mul_scale(float2 v, float2 c, float s) {
 
 __global__ __launch_bounds__(PP_THREADS) void pair_products_kernel(const float2 *__restrict__ psi_v, int nv,
                                                                    const float2 *__restrict__ psi_c, int nc, int nr,
-                                                                   const float *__restrict__ scale,
+                                                                   const float *__restrict__ scale, int ldsc,
                                                                    float2 *__restrict__ f) {
   const int c = blockIdx.x;                            // unoccupied band (fastest: blocks of one chunk run together)
   const int r0 = blockIdx.y * PP_CHUNK + 2 * threadIdx.x;
@@ -47,7 +50,7 @@ __global__ __launch_bounds__(PP_THREADS) void pair_products_kernel(const float2 
   const float2 c0 = pc[0];
   const float2 c1 = two ? pc[1] : make_float2(0.f, 0.f);
   for (int v = 0; v < nv; ++v) {
-    const float s = scale[v * nc + c];
+    const float s = scale[v * ldsc + c];
     const float2 *pv = psi_v + (size_t)v * nr + r0;
     const float2 v0 = pv[0];
     float2 *out = f + ((size_t)v * nc + c) * nr + r0;
@@ -64,9 +67,9 @@ __global__ __launch_bounds__(PP_THREADS) void pair_products_kernel(const float2 
 }
 
 hipError_t launch_pair_products(const float2 *psi_v, int nv, const float2 *psi_c, int nc, int nr, const float *scale,
-                                float2 *f, hipStream_t s) {
+                                int ldsc, float2 *f, hipStream_t s) {
   dim3 grid(nc, (nr + PP_CHUNK - 1) / PP_CHUNK);
-  hipLaunchKernelGGL(pair_products_kernel, grid, dim3(PP_THREADS), 0, s, psi_v, nv, psi_c, nc, nr, scale, f);
+  hipLaunchKernelGGL(pair_products_kernel, grid, dim3(PP_THREADS), 0, s, psi_v, nv, psi_c, nc, nr, scale, ldsc, f);
   return hipGetLastError();
 }
 

@@ -217,3 +217,26 @@ def test_workspace_cap(gw):
         gw.polarizability(c64(s.psi_v), c64(s.psi_c), s.e_v, s.e_c, s.n, s.a_bohr, s.q, s.miller, ctx=ctx)
     assert ei.value.status == 2
     ctx.close()
+
+
+# --- every tile configuration of the update ------------------------------------------------------
+def _tiles():
+    import paper_1810_07772_amd as gw
+    try:
+        return list(enumerate(gw.tile_names()))
+    except Exception:
+        return [(i, f"tile{i}") for i in range(6)]
+
+
+@pytest.mark.parametrize("n,nv,nc,r2", [(12, 8, 64, 10.0), (10, 3, 37, 6.0)])
+@pytest.mark.parametrize("tile,name", _tiles())
+def test_every_tile(gw, tile, name, n, nv, nc, r2):
+    prec = "fp32" if name.startswith("fp32") else ("bf16" if name.startswith("bf16") else "fp16")
+    tol = 1e-5 if prec == "fp32" else 1e-4
+    s = sys_c64(n, nv, nc, r2, seed=11)
+    p = gw.polarizability_r(c64(s.psi_v), c64(s.psi_c), s.e_v, s.e_c, precision=prec, tile=tile)
+    torch.cuda.synchronize()
+    ref = orc.polarizability_r(s.psi_v, s.psi_c, s.e_v, s.e_c)
+    e = orc.rel_f(p.cpu().numpy(), ref)
+    print(f"tile {name}: rel_F(P) = {e:.3e}")
+    assert e < tol
