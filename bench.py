@@ -68,6 +68,22 @@ def parity_small(gw, torch, prec):
             "eps_inv": orc.rel_f(einv.cpu().numpy(), ei)}
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "herk_bf16split_si36_pmc.md")
+PMC_KERNEL = {"bf16split_t128_ws_k32": "herk_split_ws_kernel<32, false>"}
+
+
+def measured_traffic(tile_name, workload):
+    """HBM bytes per launch of the update kernel from the committed PMC summary (FETCH_SIZE and
+    WRITE_SIZE, each scaled by a copy kernel of known size), when that summary covers this kernel."""
+    kern = PMC_KERNEL.get(tile_name)
+    if kern is None or workload != "si36" or not os.path.exists(PMC_SUMMARY):
+        return None
+    for line in open(PMC_SUMMARY):
+        if line.startswith("machine-readable: traffic_bytes_per_launch") and kern in line:
+            return float(line.split()[-1])
+    return None
+
+
 def cpu_baseline(sysd, rows, nv_sample):
     """The FP64 oracle on a bounded sample of the same workload: `rows` rows of P(r,r') summed over
     the first `nv_sample` occupied bands and every unoccupied band."""
@@ -99,6 +115,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--tile", type=int, default=-1)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy kernel first (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -133,6 +151,13 @@ def main():
     log(f"inputs resident: nr={nr} nv={nv} nc={nc} K={K} ng={ng}; P is {nr * nr * 8 / 1e9:.2f} GB")
 
     stream = torch.cuda.current_stream(dev)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del a, b
 
     def run(prec, steps, warmup):
         def one(ev=None):
@@ -201,6 +226,8 @@ def main():
         log(f"cpu baseline: {cpu}")
 
     peak = PEAK_TFLOPS["fp32" if args.precision == "fp32" else args.precision]
+    tile_name = gw.tile_names()[args.tile] if args.tile >= 0 else gw.default_tile_name(args.precision)
+    traffic = measured_traffic(tile_name, args.workload)
     out = {
         "metric": METRIC,
         "value": round(head["pbuild_tflops"], 3),
@@ -219,8 +246,9 @@ def main():
                                f"N_g={ng}, q=0, P(r,r') complex64 {nr * nr * 8 / 1e9:.1f} GB",
                    "precision": args.precision, "tile": args.tile},
         "roofline": {"bound": "mfma", "achieved": round(head["herk_tflops"], 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(head["herk_frac_peak"], 4), "traffic": None,
-                     "kernel": f"herk ({args.precision})"},
+                     "frac": round(head["herk_frac_peak"], 4), "traffic": traffic,
+                     "kernel": tile_name,
+                     "executed_frac": round(head.get("herk_executed_frac_peak", head["herk_frac_peak"]), 4)},
         "cpu_baseline": cpu,
         "precisions": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                        for k, v in results.items()},

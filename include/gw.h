@@ -97,9 +97,11 @@ const char *gw_last_error(const gw_ctx *ctx);
 /* Bytes of device workspace the context currently holds. */
 size_t gw_workspace_bytes(const gw_ctx *ctx);
 
-/* Number of tile configurations of the rank-k update kernel and the name of one. */
+/* Number of tile configurations of the rank-k update kernel, the name of one, and the one used
+ * for `precision` at grid size nr when gw_opts.tile is -1 (-1 for an unknown precision). */
 int gw_tile_count(void);
 const char *gw_tile_name(int tile);
+int gw_default_tile(int precision, int nr);
 
 /* ---------------------------------------------------------------------------
  * Pair products, Eq.(fdef):  f_out[v*nc + c][r] = conj(psi_v[v][r]) psi_c[c][r] sqrt(p/(E_c - E_v)).
@@ -124,7 +126,8 @@ int gw_polarizability_r(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *
  * Both transforms of Sec. 4.1 restricted to the sphere:
  *   p_gg[g][g'] = sum_{r,r'} exp(-i G_g.r) p_rr[r][r'] exp(+i G_g'.r').
  *   p_rr [nr][nr] complex64 (read only), g_miller host [ng][3], p_gg [ng][ng] complex64.
- *   Grid sides n_d must be in {4, 6, 8, 9, 12, 16, 18, 24, 32, 36} (else GW_E_UNSUPPORTED).
+ *   Grid sides n_d must be in {4, 5, 6, 8, 9, 10, 12, 15, 16, 18, 20, 24, 27, 30, 32, 36, 40, 48}
+ *   (else GW_E_UNSUPPORTED).
  * ------------------------------------------------------------------------- */
 int gw_sphere_transform(gw_ctx *ctx, const gw_c32 *p_rr, gw_grid grid, const int *g_miller, int ng,
                         gw_c32 *p_gg, void *stream);

@@ -18,7 +18,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "split_bf16": 1, "fp16": 2, "split_fp16": 2}
 
 # Every symbol include/gw.h declares.
 EXPORTS = ("gw_opts_default", "gw_version", "gw_status_string", "gw_create", "gw_destroy", "gw_last_error",
-           "gw_workspace_bytes", "gw_tile_count", "gw_tile_name", "gw_pair_products", "gw_polarizability_r",
+           "gw_workspace_bytes", "gw_tile_count", "gw_tile_name", "gw_default_tile", "gw_pair_products", "gw_polarizability_r",
            "gw_sphere_transform", "gw_polarizability", "gw_epsilon", "gw_eps_inverse", "gw_hpd_inverse",
            "gw_polarizability_batched")
 
@@ -64,6 +64,7 @@ def load() -> C.CDLL:
         "gw_workspace_bytes": (sz, [vp]),
         "gw_tile_count": (i, []),
         "gw_tile_name": (C.c_char_p, [i]),
+        "gw_default_tile": (i, [i, i]),
         "gw_pair_products": (i, [vp, vp, i, vp, i, i, vp, vp, d, vp, vp]),
         "gw_polarizability_r": (i, [vp, vp, i, vp, i, i, vp, vp, C.POINTER(Opts), vp, vp]),
         "gw_sphere_transform": (i, [vp, vp, Grid, vp, i, vp, vp]),
@@ -173,6 +174,12 @@ def _grid(n: Sequence[int], a_bohr: float) -> Grid:
 def tile_names():
     lib = load()
     return [lib.gw_tile_name(i).decode() for i in range(lib.gw_tile_count())]
+
+
+def default_tile_name(precision="fp32", nr=0):
+    lib = load()
+    t = lib.gw_default_tile(PRECISIONS[precision] if isinstance(precision, str) else int(precision), int(nr))
+    return lib.gw_tile_name(t).decode() if t >= 0 else ""
 
 
 # ---------------------------------------------------------------------------------------------

@@ -390,6 +390,7 @@ size_t gw_workspace_bytes(const gw_ctx *ctx) { return ctx ? ctx->held : 0; }
 
 int gw_tile_count(void) { return herk_tile_count(); }
 const char *gw_tile_name(int t) { return herk_tile_name(t); }
+int gw_default_tile(int precision, int nr) { return herk_default_tile(precision, nr); }
 
 int gw_pair_products(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *psi_c, int nc, int nr,
                      const double *e_v, const double *e_c, double prefactor, gw_c32 *f_out, void *stream) {

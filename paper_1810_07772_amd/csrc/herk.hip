@@ -403,23 +403,25 @@ __device__ __forceinline__ unsigned pk_bf16(float a, float b) {
   return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
 }
 
+template <int KW, bool PRIO>
 __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2 *__restrict__ psi_v,
                                                                      const float2 *__restrict__ psi_c,
                                                                      const float *__restrict__ scale, int ldsc,
                                                                      float2 *__restrict__ P, int nr, int nv, int nc,
                                                                      int ntiles, int accumulate) {
   typedef bf16x8 vec;
-  __shared__ __attribute__((aligned(16))) __bf16 sAh[2][HB][SROW];
-  __shared__ __attribute__((aligned(16))) __bf16 sAl[2][HB][SROW];
-  __shared__ __attribute__((aligned(16))) __bf16 sBh[2][HB][SROW];
-  __shared__ __attribute__((aligned(16))) __bf16 sBl[2][HB][SROW];
+  constexpr int SRW = 2 * KW + 8;   // narrow elements per point row (padded against bank conflicts)
+  __shared__ __attribute__((aligned(16))) __bf16 sAh[2][HB][SRW];
+  __shared__ __attribute__((aligned(16))) __bf16 sAl[2][HB][SRW];
+  __shared__ __attribute__((aligned(16))) __bf16 sBh[2][HB][SRW];
+  __shared__ __attribute__((aligned(16))) __bf16 sBl[2][HB][SRW];
 
   int bi, bj;
   tile_of(xcd_remap(blockIdx.x, ntiles), bi, bj);
   const int I0 = bi * HB, J0 = bj * HB;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform role
-  const int nchc = (nc + KS - 1) / KS;
+  const int nchc = (nc + KW - 1) / KW;
   const int nch = nv * nchc;
   const bool producer = wave >= 4;
 
@@ -431,26 +433,26 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
   // products vanish), and a point past nr only feeds output entries that are never stored, so
   // out-of-range indices are clamped to valid addresses.
   const int gpt = min((pside ? J0 : I0) + ppt, nr - 1);
-  float2 pc[KS], pcn[KS];
+  float2 pc[KW], pcn[KW];
   float2 pvv;
-  float sc[KS];
+  float sc[KW];
 
-  auto load_c = [&](float2 (&dst)[KS], int cc) {   // psi_c of chunk cc at this thread's point
+  auto load_c = [&](float2 (&dst)[KW], int cc) {   // psi_c of chunk cc at this thread's point
 #pragma unroll
-    for (int k = 0; k < KS; ++k) dst[k] = psi_c[(size_t)min(cc * KS + k, nc - 1) * nr + gpt];
+    for (int k = 0; k < KW; ++k) dst[k] = psi_c[(size_t)min(cc * KW + k, nc - 1) * nr + gpt];
   };
   auto load_v = [&](int ch) {                       // psi_v and the scales of stage ch
-    const int v = ch % nv, c0 = (ch / nv) * KS;
+    const int v = ch % nv, c0 = (ch / nv) * KW;
     pvv = psi_v[(size_t)v * nr + gpt];
     const float *srow = scale + (size_t)v * ldsc + c0;
 #pragma unroll
-    for (int k = 0; k < KS; ++k) sc[k] = srow[k];
+    for (int k = 0; k < KW; ++k) sc[k] = srow[k];
   };
   auto produce = [&](int buf) {
     u32x4 *dh = reinterpret_cast<u32x4 *>(pside ? &sBh[buf][ppt][0] : &sAh[buf][ppt][0]);
     u32x4 *dl = reinterpret_cast<u32x4 *>(pside ? &sBl[buf][ppt][0] : &sAl[buf][ppt][0]);
 #pragma unroll
-    for (int g = 0; g < KS / 4; ++g) {
+    for (int g = 0; g < KW / 4; ++g) {
       u32x4 hv, lv;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
@@ -480,7 +482,7 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
       if (ch + 1 < nch) {
         if ((ch + 1) % nv == 0) {                          // stage ch+1 opens the next unoccupied chunk
 #pragma unroll
-          for (int k = 0; k < KS; ++k) pc[k] = pcn[k];
+          for (int k = 0; k < KW; ++k) pc[k] = pcn[k];
         }
         produce((ch & 1) ^ 1);
         if (ch + 2 < nch) {
@@ -494,6 +496,7 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
   }
 
   // ---- consumer
+  if (PRIO) __builtin_amdgcn_s_setprio(2);   // favour the MFMA waves when both roles can issue
   const int wr = (wave & 3) >> 1, wc = wave & 1;
   const int kq = lane >> 5, idx = lane & 31;
   const int ar0 = wr * 64 + idx, bc0 = wc * 64 + idx;
@@ -508,7 +511,7 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
 #pragma unroll
-    for (int g = 0; g < KS / 8; ++g) {
+    for (int g = 0; g < KW / 8; ++g) {
       const int ko = g * 16 + kq * 8;
       const vec ah0 = *reinterpret_cast<const vec *>(&sAh[buf][ar0][ko]);
       const vec ah1 = *reinterpret_cast<const vec *>(&sAh[buf][ar0 + 32][ko]);
@@ -598,6 +601,9 @@ static const TileCfg kTiles[] = {
   {"fp32_t128_fold_couter", GW_FP32},
   {"bf16split_t128_couter", GW_SPLIT_BF16},
   {"bf16split_t128_ws", GW_SPLIT_BF16},
+  {"bf16split_t128_ws_k32", GW_SPLIT_BF16},
+  {"bf16split_t128_ws_prio", GW_SPLIT_BF16},
+  {"bf16split_t128_ws_k32_prio", GW_SPLIT_BF16},
 };
 
 int herk_tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -609,7 +615,7 @@ int herk_default_tile(int precision, int nr) {
   (void)nr;
   switch (precision) {
     case GW_FP32: return 4;
-    case GW_SPLIT_BF16: return 6;
+    case GW_SPLIT_BF16: return 7;
     case GW_SPLIT_FP16_SCALED: return 3;
   }
   return -1;
@@ -633,10 +639,14 @@ hipError_t launch_herk(int precision, int tile, const float2 *psi_v, const float
     case 4: GW_LAUNCH((herk_fp32_kernel<true, true>), psi_v, psi_c, scale, ldsc, p, nr, nv, nc, ntiles, accumulate); break;
     case 5: GW_LAUNCH((herk_split_kernel<__bf16, false, true>), psi_v, psi_c, scale, ldsc, band_exp, p, nr, nv, nc, ntiles,
                       accumulate); break;
-    case 6:
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_ws_kernel), grid, dim3(2 * NTHR), 0, s, psi_v, psi_c, scale,
-                         ldsc, p, nr, nv, nc, ntiles, accumulate);
-      break;
+#define GW_WS(KW_, PRIO_)                                                                                        \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_ws_kernel<KW_, PRIO_>), grid, dim3(2 * NTHR), 0, s, psi_v, psi_c, \
+                     scale, ldsc, p, nr, nv, nc, ntiles, accumulate)
+    case 6: GW_WS(16, false); break;
+    case 7: GW_WS(32, false); break;
+    case 8: GW_WS(16, true); break;
+    case 9: GW_WS(32, true); break;
+#undef GW_WS
     default:
       return hipErrorInvalidValue;
   }
