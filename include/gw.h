@@ -169,12 +169,17 @@ int gw_eps_inverse(gw_ctx *ctx, const gw_c32 *p_gg, int ng, gw_grid grid, const 
 int gw_hpd_inverse(gw_ctx *ctx, const gw_c64 *a, int n, gw_c64 *out, void *stream);
 
 /* ---------------------------------------------------------------------------
- * Batched q-points: each job j runs the whole build and eps^-1 for its own
- * unoccupied set and sphere, sharing the occupied set.  The launch sequence of
- * all jobs is captured once into a HIP graph per job shape and replayed.
- *   jobs (host) [nq]; every job pointer is a device pointer except e_c, q and
- *   g_miller (host).  P(r,r') lives in one reused workspace buffer.
- *   Synchronises `stream` (pivot flags).
+ * Batched q-points (P^q is defined per q, Eq.(staticpol)): each job j runs the
+ * whole build and eps^-1 for its own unoccupied set, energies, q and sphere,
+ * sharing the occupied set.  The launch sequence of all jobs (kernels only) is
+ * captured into one HIP graph, cached in the context and replayed while the
+ * shapes, pointers, q, sphere lists, head and options stay the same; energies
+ * are re-read on every call.  Inside the graph the update of job j+1 overlaps
+ * the transforms and inverse of job j (two P(r,r') workspace buffers).  Tiles:
+ * opts->tile if >= 0, else the tuned tile, tuning first where none is cached.
+ *   nq in [1, 64]; jobs (host) [nq]; job pointers are device pointers except
+ *   e_c and g_miller (host).  accumulate must be 0.
+ *   Synchronises `stream`; GW_E_NOTPD names the first job whose eps failed.
  * ------------------------------------------------------------------------- */
 typedef struct {
   const gw_c32 *psi_unocc;   /* [nc][nr] */
@@ -189,6 +194,20 @@ typedef struct {
 
 int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const double *e_v, gw_grid grid,
                               int nq, const gw_qjob *jobs, const gw_opts *opts, double head, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Tile autotuner of the rank-K update: times every tile of `precision` on the
+ * first min(nv, 8) occupied bands of these inputs (same N_r and Nc) and caches
+ * the fastest for (device arch, nr, nv, nc, precision) in the context (and
+ * appends it to the file named by the environment variable GW_AUTOTUNE_CACHE
+ * when set; that file is read back by later contexts).  Calls with tile = -1
+ * then use the tuned tile.  p_scratch: device [nr][nr] complex64 the timing
+ * launches overwrite.  best_tile (host) receives the choice; times_ms (host,
+ * [gw_tile_count()], optional) the time of each tile (-1 where the tile does
+ * not implement the precision).  Synchronises `stream`.
+ * ------------------------------------------------------------------------- */
+int gw_autotune(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *psi_c, int nc, int nr, const double *e_v,
+                const double *e_c, int precision, gw_c32 *p_scratch, int *best_tile, double *times_ms, void *stream);
 
 #ifdef __cplusplus
 }

@@ -31,7 +31,7 @@ import numpy as np
 __all__ = [
     "pair_products", "polarizability_r", "row_transform", "to_sphere", "coulomb_sqrt",
     "epsilon", "eps_inverse", "eps_inverse_cholesky", "newton_schulz_inverse", "adler_wiser",
-    "rel_f", "grid_phase_index",
+    "rel_f", "grid_phase_index", "adler_wiser_selected",
 ]
 
 
@@ -185,4 +185,26 @@ def adler_wiser(psi_v, psi_c, e_v, e_c, n: Sequence[int], miller, prefactor: flo
         m = np.fft.fftn(prod.reshape((-1,) + n), axes=(1, 2, 3)).reshape(len(psi_c), -1)[:, idx]  # [nc][ng]
         w = prefactor / (-de[v])                                                # p / (E_v - E_c)
         out += (m * w[:, None]).T @ np.conj(m)
+    return out
+
+
+def adler_wiser_selected(psi_v, psi_c, e_v, e_c, n: Sequence[int], miller_sel, prefactor: float = 1.0) -> np.ndarray:
+    """Eq.(gpsaceP) on a subset of sphere vectors: P~(g, g') for g, g' in `miller_sel`, with
+    M_vc(g) = sum_r exp(-i G_g.r) conj(u_c(r)) u_v(r) summed directly over the grid (no FFT),
+    one occupied band at a time.  For checks at sizes where the full P(r, r') is out of reach."""
+    n = tuple(int(x) for x in n)
+    psi_v = np.asarray(psi_v)
+    psi_c = np.asarray(psi_c)
+    m = np.asarray(miller_sel, np.float64)
+    i1, i2, i3 = np.meshgrid(*(np.arange(x) for x in n), indexing="ij")
+    ph = (np.multiply.outer(m[:, 0], i1.ravel()) / n[0] + np.multiply.outer(m[:, 1], i2.ravel()) / n[1]
+          + np.multiply.outer(m[:, 2], i3.ravel()) / n[2])
+    e = np.exp(-2j * np.pi * ph).T                                          # [nr][nsel]
+    de = np.asarray(e_c, np.float64)[None, :] - np.asarray(e_v, np.float64)[:, None]
+    out = np.zeros((len(m), len(m)), dtype=np.complex128)
+    for v in range(psi_v.shape[0]):
+        prod = np.conj(psi_c).astype(np.complex128) * psi_v[v].astype(np.complex128)[None, :]   # [nc][nr]
+        mm = prod @ e                                                         # [nc][nsel]
+        w = prefactor / (-de[v])
+        out += (mm * w[:, None]).T @ np.conj(mm)
     return out

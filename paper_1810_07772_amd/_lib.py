@@ -20,7 +20,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "split_bf16": 1, "fp16": 2, "split_fp16": 2}
 EXPORTS = ("gw_opts_default", "gw_version", "gw_status_string", "gw_create", "gw_destroy", "gw_last_error",
            "gw_workspace_bytes", "gw_tile_count", "gw_tile_name", "gw_default_tile", "gw_pair_products", "gw_polarizability_r",
            "gw_sphere_transform", "gw_polarizability", "gw_epsilon", "gw_eps_inverse", "gw_hpd_inverse",
-           "gw_polarizability_batched")
+           "gw_polarizability_batched", "gw_autotune")
 
 
 class GwError(RuntimeError):
@@ -73,6 +73,7 @@ def load() -> C.CDLL:
         "gw_eps_inverse": (i, [vp, vp, i, Grid, vp, vp, d, vp, vp]),
         "gw_hpd_inverse": (i, [vp, vp, i, vp, vp]),
         "gw_polarizability_batched": (i, [vp, vp, i, vp, Grid, i, C.POINTER(QJob), C.POINTER(Opts), d, vp]),
+        "gw_autotune": (i, [vp, vp, i, vp, i, i, vp, vp, i, vp, C.POINTER(i), vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -292,6 +293,28 @@ def hpd_inverse(a, out=None, ctx: Optional[Context] = None):
                                 _stream(a))
     ctx.check(st, "gw_hpd_inverse")
     return out
+
+
+def autotune(psi_v, psi_c, e_v, e_c, precision="bf16", p_scratch=None, ctx: Optional[Context] = None):
+    """Times every update tile of `precision` on these inputs; returns (best tile, {name: ms})."""
+    import torch
+    nv, nr = psi_v.shape
+    nc = psi_c.shape[0]
+    ctx = ctx or context(psi_v.device.index)
+    if p_scratch is None:
+        p_scratch = torch.empty((nr, nr), dtype=torch.complex64, device=psi_v.device)
+    ev, pev = _host_f64(e_v, "e_v")
+    ec, pec = _host_f64(e_c, "e_c")
+    ntile = ctx.lib.gw_tile_count()
+    times = (C.c_double * ntile)()
+    best = C.c_int(-1)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    st = ctx.lib.gw_autotune(ctx.handle, _dev(psi_v, torch.complex64, "psi_v"), nv,
+                             _dev(psi_c, torch.complex64, "psi_c"), nc, nr, pev, pec, prec,
+                             _dev(p_scratch, torch.complex64, "p_scratch"), C.byref(best), times, _stream(psi_v))
+    ctx.check(st, "gw_autotune")
+    names = tile_names()
+    return best.value, {names[t]: times[t] for t in range(ntile) if times[t] >= 0}
 
 
 def polarizability_batched(psi_v, e_v, n, a_bohr, jobs, precision="fp32", prefactor=1.0, tile=-1, head=1.0,

@@ -155,17 +155,16 @@ int check_opts(gw_ctx *ctx, const gw_opts *o) {
   return GW_OK;
 }
 
+}  // namespace
+
 // --------------------------------------------------------------------------------------------
 // Sphere-transform plan: output-row maps of the three passes (see fft.hip).
 // --------------------------------------------------------------------------------------------
-struct SpherePlan {
-  int n1, n2, n3, ng;
-  int m3count = 0, npair = 0;
-  std::vector<int> mapA, mapB, mapC;
-};
+namespace gwi {
 
-void build_plan(gw_grid g, const int *miller, int ng, SpherePlan &p) {
+void build_sphere_plan(gw_grid g, const int *miller, int ng, SpherePlan &p) {
   p.n1 = g.n1; p.n2 = g.n2; p.n3 = g.n3; p.ng = ng;
+  p.m3count = 0; p.npair = 0;
   std::vector<int> idx3(g.n3, -1);
   std::vector<int> k1s(ng), k2s(ng), k3s(ng);
   for (int i = 0; i < ng; ++i) {
@@ -200,35 +199,56 @@ void build_plan(gw_grid g, const int *miller, int ng, SpherePlan &p) {
     const int pi = pair[k2s[i] * p.m3count + idx3[k3s[i]]];
     p.mapC[(size_t)pi * g.n1 + k1s[i]] = i;
   }
+  // column chunk of the row passes so that the first intermediate stays near 1 GiB
+  const long long nr = (long long)g.n1 * g.n2 * g.n3;
+  const long long rowsA = (long long)g.n1 * g.n2 * p.m3count;
+  long long bc = std::max<long long>(256, std::min<long long>(nr, (1LL << 27) / std::max<long long>(1, rowsA)));
+  p.bc = (int)std::min<long long>(bc, nr);
+  p.a1_elems = (size_t)rowsA * p.bc;
+  p.a2_elems = (size_t)g.n1 * p.npair * p.bc;
 }
 
-// One 3-D transform over the row index of `in` ([nr][B], row stride ld_in) to `out`
-// ([ng][B], row stride ld_out), in column chunks of at most bc.
-int transform_rows(gw_ctx *ctx, const SpherePlan &p, int sign, const float2 *in, long long ld_in, int B, float2 *out,
-                   long long ld_out, float2 *a1, float2 *a2, int bc, const int *dA, const int *dB, const int *dC,
-                   hipStream_t s) {
+// One 3-D transform over the row index of `in` ([nr][B], row stride ld_in) to `out` ([ng][B],
+// row stride ld_out), in column chunks of at most bc.
+static hipError_t transform_rows(const SpherePlan &p, int sign, const float2 *in, long long ld_in, int B, float2 *out,
+                                 long long ld_out, float2 *a1, float2 *a2, int bc, const int *dA, const int *dB,
+                                 const int *dC, hipStream_t s) {
   for (int b0 = 0; b0 < B; b0 += bc) {
     const int w = std::min(bc, B - b0);
-    GW_HIP(ctx, launch_fft_pass(p.n3, sign, in + b0, a1, p.n1 * p.n2, 1, w, ld_in, w, dA, s));
-    GW_HIP(ctx, launch_fft_pass(p.n2, sign, a1, a2, p.n1, p.m3count, w, w, w, dB, s));
-    GW_HIP(ctx, launch_fft_pass(p.n1, sign, a2, out + b0, 1, p.npair, w, w, ld_out, dC, s));
+    hipError_t e;
+    if ((e = launch_fft_pass(p.n3, sign, in + b0, a1, p.n1 * p.n2, 1, w, ld_in, w, dA, s)) != hipSuccess) return e;
+    if ((e = launch_fft_pass(p.n2, sign, a1, a2, p.n1, p.m3count, w, w, w, dB, s)) != hipSuccess) return e;
+    if ((e = launch_fft_pass(p.n1, sign, a2, out + b0, 1, p.npair, w, w, ld_out, dC, s)) != hipSuccess) return e;
   }
-  return GW_OK;
+  return hipSuccess;
 }
+
+hipError_t enqueue_sphere_transform(const SpherePlan &p, const SphereBuffers &b, const float2 *p_rr, float2 *p_gg,
+                                    hipStream_t s) {
+  const int nr = p.n1 * p.n2 * p.n3, ng = p.ng;
+  hipError_t e;
+  // rows: P^(g, r') = sum_r exp(-i G.r) P(r, r')
+  if ((e = transform_rows(p, -1, p_rr, nr, nr, b.ph, nr, b.a1, b.a2, p.bc, b.dA, b.dB, b.dC, s)) != hipSuccess) return e;
+  // columns: transpose, then Q(g', g) = sum_r' exp(+i G'.r') P^T(r', g), and p_gg = Q^T
+  if ((e = launch_transpose_c64(b.ph, b.pht, ng, nr, nr, ng, s)) != hipSuccess) return e;
+  if ((e = transform_rows(p, +1, b.pht, ng, ng, b.q, ng, b.a1, b.a2, std::min(p.bc, ng), b.dA, b.dB, b.dC, s)) !=
+      hipSuccess)
+    return e;
+  return launch_transpose_c64(b.q, p_gg, ng, ng, ng, ng, s);
+}
+
+}  // namespace gwi
+
+namespace {
 
 int sphere_transform_impl(gw_ctx *ctx, const float2 *p_rr, gw_grid g, const int *miller, int ng, float2 *p_gg,
                           hipStream_t s) {
   SpherePlan plan;
-  build_plan(g, miller, ng, plan);
+  build_sphere_plan(g, miller, ng, plan);
   const int nr = g.n1 * g.n2 * g.n3;
-  // column chunk so that the first intermediate stays near 1 GiB
-  const long long rowsA = (long long)g.n1 * g.n2 * plan.m3count;
-  int bc = (int)std::max<long long>(256, std::min<long long>(nr, (1LL << 27) / std::max<long long>(1, rowsA)));
-  bc = std::min(bc, nr);
-  const long long rowsB = (long long)g.n1 * plan.npair;
   void *a1, *a2, *maps, *ph, *pht, *q;
-  GW_STATUS(ws_get(ctx, WS_FFT_A, (size_t)rowsA * bc * sizeof(float2), &a1, s));
-  GW_STATUS(ws_get(ctx, WS_FFT_B, (size_t)rowsB * bc * sizeof(float2), &a2, s));
+  GW_STATUS(ws_get(ctx, WS_FFT_A, plan.a1_elems * sizeof(float2), &a1, s));
+  GW_STATUS(ws_get(ctx, WS_FFT_B, plan.a2_elems * sizeof(float2), &a2, s));
   const size_t nA = plan.mapA.size(), nB = plan.mapB.size(), nC = plan.mapC.size();
   GW_STATUS(ws_get(ctx, WS_FFT_MAP, (nA + nB + nC) * sizeof(int), &maps, s));
   GW_STATUS(ws_get(ctx, WS_COUNT_BASE + 0, (size_t)ng * nr * sizeof(float2), &ph, s));
@@ -238,15 +258,8 @@ int sphere_transform_impl(gw_ctx *ctx, const float2 *p_rr, gw_grid g, const int 
   GW_HIP(ctx, hipMemcpyAsync(dA, plan.mapA.data(), nA * sizeof(int), hipMemcpyHostToDevice, s));
   GW_HIP(ctx, hipMemcpyAsync(dB, plan.mapB.data(), nB * sizeof(int), hipMemcpyHostToDevice, s));
   GW_HIP(ctx, hipMemcpyAsync(dC, plan.mapC.data(), nC * sizeof(int), hipMemcpyHostToDevice, s));
-  // rows: P^(g, r') = sum_r exp(-i G.r) P(r, r')
-  GW_STATUS(transform_rows(ctx, plan, -1, p_rr, nr, nr, (float2 *)ph, nr, (float2 *)a1, (float2 *)a2, bc, dA, dB, dC,
-                           s));
-  // columns: transpose, then Q(g', g) = sum_r' exp(+i G'.r') P^T(r', g), and p_gg = Q^T
-  GW_HIP(ctx, launch_transpose_c64((const float2 *)ph, (float2 *)pht, ng, nr, nr, ng, s));
-  const int bc2 = std::min(bc, ng);
-  GW_STATUS(transform_rows(ctx, plan, +1, (const float2 *)pht, ng, ng, (float2 *)q, ng, (float2 *)a1, (float2 *)a2,
-                           bc2, dA, dB, dC, s));
-  GW_HIP(ctx, launch_transpose_c64((const float2 *)q, p_gg, ng, ng, ng, ng, s));
+  SphereBuffers b{(float2 *)a1, (float2 *)a2, (float2 *)ph, (float2 *)pht, (float2 *)q, dA, dB, dC};
+  GW_HIP(ctx, enqueue_sphere_transform(plan, b, p_rr, p_gg, s));
   return GW_OK;
 }
 
@@ -275,7 +288,9 @@ int polarizability_r_impl(gw_ctx *ctx, const float2 *psi_v, int nv, const float2
     bexp = (int *)b;
     GW_HIP(ctx, launch_band_exponents(psi_v, nv, psi_c, nc, nr, scale, scale_ld(nc), bexp, s));
   }
-  GW_HIP(ctx, launch_herk(o.precision, o.tile, psi_v, psi_c, scale, scale_ld(nc), bexp, p_rr, nr, nv, nc, o.accumulate, s));
+  int tile = o.tile;
+  if (tile < 0) tile = tuned_tile(ctx, nr, nv, nc, o.precision);   // -1 when nothing is tuned: the default
+  GW_HIP(ctx, launch_herk(o.precision, tile, psi_v, psi_c, scale, scale_ld(nc), bexp, p_rr, nr, nv, nc, o.accumulate, s));
   return GW_OK;
 }
 

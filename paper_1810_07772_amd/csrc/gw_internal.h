@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,9 @@ struct gw_ctx {
   std::vector<Slot> slots;    // grow-only named workspace buffers
   int *pivot_host = nullptr;  // pinned host word for the Cholesky pivot flag
   void *graph_cache = nullptr;  // batched-q graphs (owned; see gw_batched.cpp)
+  std::map<std::string, int> tuned;   // autotuned update tiles, keyed by arch and shape
+  bool tune_loaded = false;           // the autotune cache file has been read
+  std::string arch;                   // device architecture name (cached)
 };
 
 namespace gwi {
@@ -84,5 +88,37 @@ hipError_t launch_fill_int(int *p, int value, hipStream_t s);
 
 // Releases the batched-q graphs a context holds.
 void batched_release(gw_ctx *ctx);
+
+// ---- sphere-transform plan (host) and its launch sequence (kernels only) -----------------------
+struct SpherePlan {
+  int n1 = 0, n2 = 0, n3 = 0, ng = 0;
+  int m3count = 0, npair = 0;
+  std::vector<int> mapA, mapB, mapC;
+  int bc = 0;                      // column chunk of the row passes
+  size_t a1_elems = 0, a2_elems = 0;
+};
+void build_sphere_plan(gw_grid g, const int *miller, int ng, SpherePlan &p);
+struct SphereBuffers {
+  float2 *a1, *a2, *ph, *pht, *q;  // pass intermediates, P^ [ng][nr], its transpose, Q [ng][ng]
+  const int *dA, *dB, *dC;         // device copies of the plan's maps
+};
+hipError_t enqueue_sphere_transform(const SpherePlan &p, const SphereBuffers &b, const float2 *p_rr, float2 *p_gg,
+                                    hipStream_t s);
+
+// ---- shared host helpers of gw_api.cpp used by the batched path ---------------------------------
+int api_ws_get(gw_ctx *ctx, int slot, size_t bytes, void **out, hipStream_t s);
+int api_check_energies(gw_ctx *ctx, const double *e_v, int nv, const double *e_c, int nc);
+int api_check_sphere(gw_ctx *ctx, gw_grid g, const int *m, int ng);
+int api_check_opts(gw_ctx *ctx, const gw_opts *o);
+int api_check_grid(gw_ctx *ctx, gw_grid g);
+int api_grid_supported(gw_ctx *ctx, gw_grid g);
+int api_begin(gw_ctx *ctx);
+void api_set_err(gw_ctx *ctx, const char *msg);
+
+// ---- tile autotuner --------------------------------------------------------------------------------
+// Tuned tile for (nr, nv, nc, precision) on the context's device, or -1 if none is cached.
+int tuned_tile(gw_ctx *ctx, int nr, int nv, int nc, int precision);
+int autotune_impl(gw_ctx *ctx, const float2 *psi_v, int nv, const float2 *psi_c, int nc, int nr, const double *e_v,
+                  const double *e_c, int precision, float2 *p_scratch, int *best, double *times_ms, hipStream_t s);
 
 }  // namespace gwi

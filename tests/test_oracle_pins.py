@@ -62,6 +62,15 @@ def test_p2_rspace_equals_adler_wiser(n, nv, nc, r2, q):
     assert orc.rel_f(pt, aw) < 1e-13
 
 
+def test_p2_selected_entries_equal_full_route():
+    """The direct-sum Adler-Wiser on a subset of G equals the FFT-based full route on that subset."""
+    s = gs.make_system(8, 3, 10, r2_psi=6.0, seed=23, q=(0.05, 0.0, -0.1))
+    sel = np.array([0, 3, 7, 20, len(s.miller) - 1])
+    full = orc.adler_wiser(s.psi_v, s.psi_c, s.e_v, s.e_c, s.n, s.miller)
+    part = orc.adler_wiser_selected(s.psi_v, s.psi_c, s.e_v, s.e_c, s.n, s.miller[sel])
+    assert np.max(np.abs(part - full[np.ix_(sel, sel)])) < 1e-13 * np.max(np.abs(full))
+
+
 # --- P3: plane-wave closed form -------------------------------------------------------
 def test_p3_plane_wave_closed_form():
     """Plane-wave orbitals: P~ is diagonal with P~(g,g) = -p sum_{vc: m_v - m_c = m_g (mod n)} 1/(E_c-E_v).
