@@ -222,3 +222,38 @@ def make_batched_q(n: int = 32, nv: int = 96, nc: int = 768, r2_psi: float = 81.
         _, ecj = energies(rng, nv, nc)
         jobs.append(dict(psi_c=psij[nv:].copy(), e_c=ecj, q=qs[j], miller=sphere(grid, q=qs[j], count=sizes[j])))
     return dict(n=grid, a_bohr=cell_side(n), psi_v=psi0[:nv].copy(), e_v=ev, jobs=jobs)
+
+
+# ---------------------------------------------------------------------------
+# Learned band tail: seeded initial parameters and the training / evaluation systems
+# ---------------------------------------------------------------------------
+TAIL_SHAPES = [("w1", (4, 128)), ("b1", (128,)), ("w2", (128, 128)), ("b2", (128,)), ("w3", (128, 33)),
+               ("b3", (33,))]
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Flat float32 initial parameters (W1, b1, W2, b2, W3, b3): weights N(0, 1/fan_in), the last
+    layer scaled by 0.1, biases zero except b3[0] = -2 (a small initial diagonal correction)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shp in TAIL_SHAPES:
+        if name.startswith("w"):
+            a = rng.standard_normal(shp) / np.sqrt(shp[0])
+            if name == "w3":
+                a *= 0.1
+        else:
+            a = np.zeros(shp)
+            if name == "b3":
+                a[0] = -2.0
+        parts.append(a.ravel())
+    return np.concatenate(parts).astype(np.float32)
+
+
+def tail_train_system(seed: int, n: int = 16, nv: int = 32, nc_full: int = 512, r2: float = 36.0) -> System:
+    """A training system: 16^3 grid, 925-vector sphere, the full unoccupied set of 512 bands."""
+    return make_system(n, nv, nc_full, r2_psi=r2, seed=seed)
+
+
+def tail_eval_system(seed: int, n: int = 24, nv: int = 32, nc_full: int = 1024, r2: float = 81.0) -> System:
+    """An evaluation system: 24^3 grid, 3071-vector sphere, 1024 unoccupied bands."""
+    return make_system(n, nv, nc_full, r2_psi=r2, seed=seed)

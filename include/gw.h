@@ -209,6 +209,67 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
 int gw_autotune(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *psi_c, int nc, int nr, const double *e_v,
                 const double *e_c, int precision, gw_c32 *p_scratch, int *best_tile, double *times_ms, void *stream);
 
+/* ===========================================================================
+ * Learned band-tail correction of the truncated unoccupied-band sum (the band
+ * truncation the paper lists as the first technical issue of Eq.(Pstatic)).
+ *   features x_G = (|q+G| [1/Bohr], log|Re P~_Nc(G,G)|, Nc/N_g, E_max [Ha]),
+ *   o_G = MLP(x_G): 4 -> 128 -> 128 -> 33, SiLU, BF16 weights, FP32 arithmetic,
+ *         inputs normalised by the stored mean and std,
+ *   s_G = |Re P~_Nc(G,G)|, d_G = softplus(o_G0) s_G, u_Gk = (o_G,1+k + i o_G,17+k) sqrt(s_G),
+ *   dP~ = -(diag(d) + U U^H)  (negative semidefinite, like the missing tail),
+ *   training loss ||dP~ - T||_F^2 / ||T||_F^2 with T = H(P~_4Nc) - H(P~_Nc), H(X) = (X + X^H)/2,
+ *   minimised with Adam on an FP32 master copy of the parameters.
+ * ========================================================================= */
+#define GW_TAIL_NWEIGHT 21120  /* 4*128 + 128*128 + 128*33 BF16 weights                       */
+#define GW_TAIL_NBIAS 289      /* 128 + 128 + 33 FP32 biases                                  */
+#define GW_TAIL_NPARAM 21409   /* master layout: W1[4][128] b1 W2[128][128] b2 W3[128][33] b3  */
+
+typedef struct {
+  void *w;        /* device BF16 [GW_TAIL_NWEIGHT]: W1, W2, W3, each [inputs][outputs] row-major   */
+  float *b;       /* device FP32 [GW_TAIL_NBIAS]: b1, b2, b3                                      */
+  float *norm;    /* device FP32 [16]: feature mean[4], std[4], training box lo[4], hi[4] (raw)   */
+} gw_mlp;
+
+typedef struct {
+  float *master;  /* device FP32 [GW_TAIL_NPARAM] parameters (master copy)                        */
+  float *m, *v;   /* device FP32 [GW_TAIL_NPARAM] Adam moments (zero-initialised by the caller)     */
+  float *grad;    /* device FP32 [GW_TAIL_NPARAM] gradient of the last step (written)             */
+  int step;       /* steps taken so far; each train step increments it                            */
+  float lr, beta1, beta2, eps;
+} gw_adam;
+
+/* Writes w->w (BF16, round to nearest even) and w->b from an FP32 master copy [GW_TAIL_NPARAM]. */
+int gw_tail_init(gw_ctx *ctx, gw_mlp *w, const float *master, void *stream);
+
+/* Training target T = H(p_full) - H(p_trunc), all [ng][ng] complex64. */
+int gw_tail_target(gw_ctx *ctx, const gw_c32 *p_full, const gw_c32 *p_trunc, int ng, gw_c32 *target, void *stream);
+
+/* Raw features [ng][4] of the truncated build p_gg (nc unoccupied bands, highest energy e_max in
+ * Hartree) on the sphere g_miller (host) around q (host). */
+int gw_tail_features(gw_ctx *ctx, const gw_c32 *p_gg, int ng, gw_grid grid, const double *q, const int *g_miller,
+                     int nc, double e_max, float *feat, void *stream);
+
+/* MLP outputs o [ng][33] for raw features feat [ng][4]. */
+int gw_tail_forward(gw_ctx *ctx, const gw_mlp *w, const float *feat, int ng, float *out, void *stream);
+
+/* One training step on one system: forward, loss (written to the device float *loss_out),
+ * gradient (opt->grad), Adam update of opt->master and refresh of w->w, w->b; opt->step += 1.
+ * target [ng][ng] must be Hermitian (as gw_tail_target makes it). */
+int gw_tail_train_step(gw_ctx *ctx, gw_mlp *w, gw_adam *opt, const float *feat, const gw_c32 *target, int ng,
+                       float *loss_out, void *stream);
+
+/* The training loss of the current weights on one system, into the device float *loss_out
+ * (forward and loss only; no gradient, no update). */
+int gw_tail_loss(gw_ctx *ctx, const gw_mlp *w, const float *feat, const gw_c32 *target, int ng, float *loss_out,
+                 void *stream);
+
+/* Corrected build p_corr = p_trunc + dP~ [ng][ng].  If any feature lies outside the training box
+ * widened by 5% of its width on each side, *used_fallback (host) is set to 1, p_corr is not
+ * written, and the caller runs the plain larger-Nc build instead; otherwise *used_fallback = 0.
+ * Synchronises `stream`. */
+int gw_tail_correct(gw_ctx *ctx, const gw_mlp *w, const gw_c32 *p_trunc, int ng, const float *feat, gw_c32 *p_corr,
+                    int *used_fallback, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

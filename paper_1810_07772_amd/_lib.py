@@ -20,7 +20,9 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "split_bf16": 1, "fp16": 2, "split_fp16": 2}
 EXPORTS = ("gw_opts_default", "gw_version", "gw_status_string", "gw_create", "gw_destroy", "gw_last_error",
            "gw_workspace_bytes", "gw_tile_count", "gw_tile_name", "gw_default_tile", "gw_pair_products", "gw_polarizability_r",
            "gw_sphere_transform", "gw_polarizability", "gw_epsilon", "gw_eps_inverse", "gw_hpd_inverse",
-           "gw_polarizability_batched", "gw_autotune")
+           "gw_polarizability_batched", "gw_autotune", "gw_tail_init", "gw_tail_target", "gw_tail_features",
+           "gw_tail_forward", "gw_tail_train_step", "gw_tail_loss", "gw_tail_correct")
+TAIL_NWEIGHT, TAIL_NBIAS, TAIL_NPARAM = 21120, 289, 21409
 
 
 class GwError(RuntimeError):
@@ -35,6 +37,15 @@ class Opts(C.Structure):
 
 class Grid(C.Structure):
     _fields_ = [("n1", C.c_int), ("n2", C.c_int), ("n3", C.c_int), ("a_bohr", C.c_double)]
+
+
+class Mlp(C.Structure):
+    _fields_ = [("w", C.c_void_p), ("b", C.c_void_p), ("norm", C.c_void_p)]
+
+
+class Adam(C.Structure):
+    _fields_ = [("master", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("grad", C.c_void_p),
+                ("step", C.c_int), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
 
 
 class QJob(C.Structure):
@@ -74,6 +85,13 @@ def load() -> C.CDLL:
         "gw_hpd_inverse": (i, [vp, vp, i, vp, vp]),
         "gw_polarizability_batched": (i, [vp, vp, i, vp, Grid, i, C.POINTER(QJob), C.POINTER(Opts), d, vp]),
         "gw_autotune": (i, [vp, vp, i, vp, i, i, vp, vp, i, vp, C.POINTER(i), vp, vp]),
+        "gw_tail_init": (i, [vp, C.POINTER(Mlp), vp, vp]),
+        "gw_tail_target": (i, [vp, vp, vp, i, vp, vp]),
+        "gw_tail_features": (i, [vp, vp, i, Grid, vp, vp, i, d, vp, vp]),
+        "gw_tail_forward": (i, [vp, C.POINTER(Mlp), vp, i, vp, vp]),
+        "gw_tail_train_step": (i, [vp, C.POINTER(Mlp), C.POINTER(Adam), vp, vp, i, vp, vp]),
+        "gw_tail_correct": (i, [vp, C.POINTER(Mlp), vp, i, vp, vp, C.POINTER(i), vp]),
+        "gw_tail_loss": (i, [vp, C.POINTER(Mlp), vp, vp, i, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -346,3 +364,107 @@ def polarizability_batched(psi_v, e_v, n, a_bohr, jobs, precision="fp32", prefac
                                            _stream(psi_v))
     ctx.check(st, "gw_polarizability_batched")
     return jobs
+
+
+# ---------------------------------------------------------------------------------------------
+# learned band tail
+# ---------------------------------------------------------------------------------------------
+class TailModel:
+    """Device state of the band-tail MLP: BF16 weights, FP32 biases, feature normalisation and
+    training box, and the Adam state on an FP32 master copy."""
+
+    def __init__(self, master, norm, device="cuda:0", lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                 ctx: Optional[Context] = None):
+        import torch
+        dev = torch.device(device)
+        self.ctx = ctx or context(dev.index if dev.index is not None else 0)
+        self.w = torch.empty(TAIL_NWEIGHT, dtype=torch.bfloat16, device=dev)
+        self.b = torch.empty(TAIL_NBIAS, dtype=torch.float32, device=dev)
+        self.norm = torch.as_tensor(np.asarray(norm, np.float32)).to(dev).contiguous()
+        self.master = torch.as_tensor(np.asarray(master, np.float32)).to(dev).contiguous()
+        self.m = torch.zeros(TAIL_NPARAM, dtype=torch.float32, device=dev)
+        self.v = torch.zeros(TAIL_NPARAM, dtype=torch.float32, device=dev)
+        self.grad = torch.zeros(TAIL_NPARAM, dtype=torch.float32, device=dev)
+        self.adam = Adam(C.c_void_p(self.master.data_ptr()), C.c_void_p(self.m.data_ptr()),
+                         C.c_void_p(self.v.data_ptr()), C.c_void_p(self.grad.data_ptr()), 0, lr, beta1, beta2, eps)
+        self.mlp = Mlp(C.c_void_p(self.w.data_ptr()), C.c_void_p(self.b.data_ptr()),
+                       C.c_void_p(self.norm.data_ptr()))
+        st = self.ctx.lib.gw_tail_init(self.ctx.handle, C.byref(self.mlp), C.c_void_p(self.master.data_ptr()),
+                                       _stream(self.master))
+        self.ctx.check(st, "gw_tail_init")
+
+    @property
+    def step(self):
+        return self.adam.step
+
+    def forward(self, feat, out=None):
+        import torch
+        ng = feat.shape[0]
+        if out is None:
+            out = torch.empty((ng, 33), dtype=torch.float32, device=feat.device)
+        st = self.ctx.lib.gw_tail_forward(self.ctx.handle, C.byref(self.mlp), _dev(feat, torch.float32, "feat"), ng,
+                                          _dev(out, torch.float32, "out"), _stream(feat))
+        self.ctx.check(st, "gw_tail_forward")
+        return out
+
+    def train_step(self, feat, target, loss_out=None):
+        import torch
+        ng = feat.shape[0]
+        if loss_out is None:
+            loss_out = torch.empty(1, dtype=torch.float32, device=feat.device)
+        st = self.ctx.lib.gw_tail_train_step(self.ctx.handle, C.byref(self.mlp), C.byref(self.adam),
+                                             _dev(feat, torch.float32, "feat"), _dev(target, torch.complex64, "target"),
+                                             ng, _dev(loss_out, torch.float32, "loss_out"), _stream(feat))
+        self.ctx.check(st, "gw_tail_train_step")
+        return loss_out
+
+    def loss(self, feat, target, loss_out=None):
+        import torch
+        ng = feat.shape[0]
+        if loss_out is None:
+            loss_out = torch.empty(1, dtype=torch.float32, device=feat.device)
+        st = self.ctx.lib.gw_tail_loss(self.ctx.handle, C.byref(self.mlp), _dev(feat, torch.float32, "feat"),
+                                       _dev(target, torch.complex64, "target"), ng,
+                                       _dev(loss_out, torch.float32, "loss_out"), _stream(feat))
+        self.ctx.check(st, "gw_tail_loss")
+        return loss_out
+
+    def correct(self, p_trunc, feat, out=None):
+        """Returns (p_corr, used_fallback); with the fallback p_corr is None."""
+        import torch
+        ng = p_trunc.shape[0]
+        if out is None:
+            out = torch.empty_like(p_trunc)
+        fb = C.c_int(0)
+        st = self.ctx.lib.gw_tail_correct(self.ctx.handle, C.byref(self.mlp), _dev(p_trunc, torch.complex64, "p_trunc"),
+                                          ng, _dev(feat, torch.float32, "feat"), _dev(out, torch.complex64, "p_corr"),
+                                          C.byref(fb), _stream(p_trunc))
+        self.ctx.check(st, "gw_tail_correct")
+        return (None, True) if fb.value else (out, False)
+
+
+def tail_target(p_full, p_trunc, out=None, ctx: Optional[Context] = None):
+    import torch
+    ng = p_full.shape[0]
+    if out is None:
+        out = torch.empty_like(p_full)
+    ctx = ctx or context(p_full.device.index)
+    st = ctx.lib.gw_tail_target(ctx.handle, _dev(p_full, torch.complex64, "p_full"),
+                                _dev(p_trunc, torch.complex64, "p_trunc"), ng, _dev(out, torch.complex64, "target"),
+                                _stream(p_full))
+    ctx.check(st, "gw_tail_target")
+    return out
+
+
+def tail_features(p_gg, n, a_bohr, q, miller, nc, e_max, out=None, ctx: Optional[Context] = None):
+    import torch
+    m, pm = _host_i32(miller, "g_miller")
+    ng = m.shape[0]
+    qa, pq = _host_f64(q, "q")
+    if out is None:
+        out = torch.empty((ng, 4), dtype=torch.float32, device=p_gg.device)
+    ctx = ctx or context(p_gg.device.index)
+    st = ctx.lib.gw_tail_features(ctx.handle, _dev(p_gg, torch.complex64, "p_gg"), ng, _grid(n, a_bohr), pq, pm,
+                                  int(nc), float(e_max), _dev(out, torch.float32, "feat"), _stream(p_gg))
+    ctx.check(st, "gw_tail_features")
+    return out

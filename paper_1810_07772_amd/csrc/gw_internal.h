@@ -43,6 +43,8 @@ enum SlotId {
   WS_CHOL_SMALL,  // diagonal-block inverses + pivot flag
   WS_BSCALE,      // per-band power-of-two exponents (FP16 path)
   WS_PGG_T,       // complex64 [ng][ng] transposed sphere result
+  WS_TAIL,        // learned-tail intermediates
+  WS_TAIL_FLAG,   // training-box flag
   WS_COUNT_BASE
 };
 
@@ -85,6 +87,21 @@ size_t chol_small_bytes(int n);
 hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small, int *pivot_dev, double2 *out,
                        hipStream_t s);
 hipError_t launch_fill_int(int *p, int value, hipStream_t s);
+
+// Learned band-tail correction (tail.hip).
+size_t tail_ws_floats(int n);
+hipError_t tail_features(const float2 *p, int ng, const int *miller, const double *q, double a_bohr, int nc,
+                         double e_max, float *feat, hipStream_t s);
+hipError_t tail_target(const float2 *full, const float2 *trunc, int ng, float2 *t, hipStream_t s);
+hipError_t tail_forward(const gw_mlp &w, const float *feat, int n, float *ws, float *out, hipStream_t s);
+hipError_t tail_train_step(gw_mlp &w, gw_adam &a, const float *feat, const float2 *target, int n, float *ws,
+                           float *loss_out, hipStream_t s);
+hipError_t tail_sync_weights(gw_mlp &w, const float *master, hipStream_t s);
+hipError_t tail_loss(const gw_mlp &w, const float *feat, const float2 *target, int n, float *ws, float *loss_out,
+                     hipStream_t s);
+hipError_t tail_check_box(const float *feat, int n, const float *norm, int *flag, hipStream_t s);
+hipError_t tail_apply(const gw_mlp &w, const float *feat, const float2 *p, int n, float *ws, float2 *out,
+                      hipStream_t s);
 
 // Releases the batched-q graphs a context holds.
 void batched_release(gw_ctx *ctx);
