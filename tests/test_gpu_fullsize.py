@@ -1,0 +1,66 @@
+"""Parity at the production size, in the launch configuration the benchmark times: the 36^3 workload
+(N_r = 46656, Nv = 128, Nc = 1024, K = 131072, N_g = 4067, P(r,r') = 17.4 GB).  The oracle computes
+sampled outputs one by one: rows of P over the full K, P~ entries on selected G by the direct-sum
+Adler-Wiser route, and eps^-1 by LU of the eps the library builds."""
+import time
+
+import numpy as np
+import pytest
+
+import gwsynth as gs
+import oracle as orc
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+ROWS = np.array([0, 1, 777, 23328, 46655])         # first, second, interior, centre, last grid point
+GSEL = np.array([0, 1, 6, 100, 2033, 4066])
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1810_07772_amd as gw
+    gw.load()
+    t0 = time.time()
+    s = gs.make_system(36, 128, 1024, r2_psi=98.0, seed=0)
+    pv64, pc64 = s.psi_v.astype(np.complex64), s.psi_c.astype(np.complex64)
+    print(f"[case] 36^3 inputs generated in {time.time() - t0:.1f} s", flush=True)
+    rows_ref = orc.polarizability_r(pv64, pc64, s.e_v, s.e_c, rows=ROWS)
+    print(f"[case] oracle rows done at {time.time() - t0:.1f} s", flush=True)
+    pt_ref = orc.adler_wiser_selected(pv64, pc64, s.e_v, s.e_c, s.n, s.miller[GSEL])
+    print(f"[case] oracle P~ entries done at {time.time() - t0:.1f} s", flush=True)
+    dev = torch.device("cuda:0")
+    pv = torch.from_numpy(pv64).to(dev)
+    pc = torch.from_numpy(pc64).to(dev)
+    prr = torch.empty((s.nr, s.nr), dtype=torch.complex64, device=dev)
+    return dict(gw=gw, s=s, pv=pv, pc=pc, prr=prr, rows_ref=rows_ref, pt_ref=pt_ref)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 1e-4)])
+def test_production_size(setup, prec, tol):
+    gw, s, prr = setup["gw"], setup["s"], setup["prr"]
+    print(f"[case] 36^3 build, {prec}", flush=True)
+    pgg = gw.polarizability(setup["pv"], setup["pc"], s.e_v, s.e_c, s.n, s.a_bohr, s.q, s.miller, precision=prec,
+                            p_rr=prr)
+    einv = gw.eps_inverse(pgg, s.n, s.a_bohr, s.q, s.miller)
+    torch.cuda.synchronize()
+    rows = prr[torch.from_numpy(ROWS).to(prr.device)].cpu().numpy()
+    e_rows = orc.rel_f(rows, setup["rows_ref"])
+    pt = pgg.cpu().numpy()
+    e_pt = orc.rel_f(pt[np.ix_(GSEL, GSEL)], setup["pt_ref"])
+    # Hermitian symmetry of the sampled rows against the columns the kernel wrote separately
+    cols = prr[:, torch.from_numpy(ROWS).to(prr.device)].cpu().numpy().T
+    herm = np.max(np.abs(rows - np.conj(cols))) / np.max(np.abs(rows))
+    pth = 0.5 * (pt.astype(np.complex128) + pt.astype(np.complex128).conj().T)
+    ei_ref = orc.eps_inverse(orc.epsilon(pth, orc.coulomb_sqrt(s.n, s.a_bohr, s.q, s.miller)))
+    e_inv = orc.rel_f(einv.cpu().numpy(), ei_ref)
+    print(f"{prec}: rel_F P rows {e_rows:.2e}, P~ entries {e_pt:.2e}, eps^-1 vs LU {e_inv:.2e}, "
+          f"row/column asymmetry {herm:.1e}")
+    assert e_rows < tol and e_pt < tol
+    # off the diagonal tiles the mirror is written exactly; inside them the two halves are summed
+    # separately, so they may differ at the rounding level of the precision
+    assert herm <= 0.1 * tol
+    assert e_inv < 1e-10
