@@ -210,6 +210,54 @@ def main():
         results[prec] = run(prec, args.steps, args.warmup)
     head = results[args.precision]
 
+    # standalone pair products (the fused update never stores them): one block of 8 occupied bands
+    pp = None
+    if args.workload == "si36":
+        nvb = 8
+        f = torch.empty((nvb * nc, nr), dtype=torch.complex64, device=dev)
+        pvb = pv[:nvb].contiguous()
+        for _ in range(2):
+            gw.pair_products(pvb, pc, s.e_v[:nvb], s.e_c, out=f)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record(stream)
+        for _ in range(reps):
+            gw.pair_products(pvb, pc, s.e_v[:nvb], s.e_c, out=f)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / reps
+        nbytes = 8.0 * (nvb * nc * nr + (nvb + nc) * nr)      # write F once, read psi once
+        pp = {"bound": "hbm", "achieved": round(nbytes / t / 1e9, 1), "peak": HBM_GBS, "unit": "GB/s",
+              "frac": round(nbytes / t / 1e9 / HBM_GBS, 4), "kernel": "pair_products_kernel",
+              "unit_work": f"{nvb} occupied x {nc} unoccupied bands x {nr} points, {nbytes / 1e9:.2f} GB",
+              "ms": round(t * 1e3, 3)}
+        log(f"pair products: {t * 1e3:.2f} ms, {nbytes / t / 1e9:.0f} GB/s")
+        del f
+
+    # eps^-1 two ways at N_g: the FP64 Cholesky route the step times (about 4 N_g^3 flops) and the
+    # Newton iteration of Sec. 5.1 (8 N_g^3 for A A^H, then 16 N_g^3 per iteration), both on FP64 MFMA
+    chol = {"bound": "mfma", "achieved": round(4.0 * ng ** 3 / head["eps_inverse_s"] / 1e12, 2),
+            "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+            "frac": round(4.0 * ng ** 3 / head["eps_inverse_s"] / 1e12 / PEAK_TFLOPS["fp64"], 4),
+            "ms": round(head["eps_inverse_s"] * 1e3, 2)}
+    newton = None
+    if args.workload == "si36":
+        xn = torch.empty_like(einv)
+        gw.eps_inverse_newton(pgg, s.n, s.a_bohr, s.q, s.miller, tol=1e-11, out=xn)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        _, its, hist = gw.eps_inverse_newton(pgg, s.n, s.a_bohr, s.q, s.miller, tol=1e-11, out=xn)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3
+        fl = 8.0 * ng ** 3 * (1 + 2 * its)
+        newton = {"bound": "mfma", "achieved": round(fl / t / 1e12, 2), "peak": PEAK_TFLOPS["fp64"],
+                  "unit": "TFLOP/s", "frac": round(fl / t / 1e12 / PEAK_TFLOPS["fp64"], 4), "iterations": its,
+                  "tol": 1e-11, "last_change": hist[-1], "ms": round(t * 1e3, 2),
+                  "max_abs_vs_cholesky": float((xn - einv).abs().max().item())}
+        log(f"Newton eps^-1: {its} iterations, {t * 1e3:.1f} ms, {fl / t / 1e12:.1f} TFLOP/s")
+        del xn
+
     parity = {}
     if not args.no_parity:
         for prec in [args.precision] + compare:
@@ -257,6 +305,9 @@ def main():
         "parity_12cubed_relF": parity,
         "transforms_roofline": {"bound": "hbm", "achieved": round(head["transforms_gbs"], 1), "peak": HBM_GBS,
                                 "unit": "GB/s", "frac": round(head["transforms_gbs"] / HBM_GBS, 4)},
+        "pair_products_roofline": pp,
+        "eps_inverse_cholesky_roofline": chol,
+        "eps_inverse_newton": newton,
     }
     print(json.dumps(out), flush=True)
 

@@ -169,6 +169,25 @@ int gw_eps_inverse(gw_ctx *ctx, const gw_c32 *p_gg, int ng, gw_grid grid, const 
 int gw_hpd_inverse(gw_ctx *ctx, const gw_c64 *a, int n, gw_c64 *out, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Inverse by the Newton iteration of Sec. 5.1, for any nonsingular complex128
+ * a[n][n]:  X_{n+1} = X_n (2I - A X_n), X_0 = alpha A^H with
+ * alpha = 1 / max_i sum_j |(A A^H)_ij| (absolute values, so that the iteration
+ * converges); stops when max_ij |X_{n+1} - X_n| < tol.  Every product runs on
+ * the FP64 MFMA GEMM.  *iterations (host) receives the iteration count and
+ * history (host, optional, [max_iter]) the max change of each iteration.
+ * Synchronises `stream` once per iteration.  Returns GW_E_UNSUPPORTED if tol is
+ * not reached in max_iter iterations (out then holds the last iterate) and
+ * GW_E_NOTPD if the iteration diverges.
+ * ------------------------------------------------------------------------- */
+int gw_newton_inverse(gw_ctx *ctx, const gw_c64 *a, int n, double tol, int max_iter, gw_c64 *out, int *iterations,
+                      double *history, void *stream);
+
+/* eps^-1 as gw_eps_inverse, but by the Newton iteration above (the paper's method). */
+int gw_eps_inverse_newton(gw_ctx *ctx, const gw_c32 *p_gg, int ng, gw_grid grid, const double *q, const int *g_miller,
+                          double head, double tol, int max_iter, gw_c64 *eps_inv, int *iterations, double *history,
+                          void *stream);
+
+/* ---------------------------------------------------------------------------
  * Batched q-points (P^q is defined per q, Eq.(staticpol)): each job j runs the
  * whole build and eps^-1 for its own unoccupied set, energies, q and sphere,
  * sharing the occupied set.  The launch sequence of all jobs (kernels only) is

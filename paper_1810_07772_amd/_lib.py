@@ -21,7 +21,8 @@ EXPORTS = ("gw_opts_default", "gw_version", "gw_status_string", "gw_create", "gw
            "gw_workspace_bytes", "gw_tile_count", "gw_tile_name", "gw_default_tile", "gw_pair_products", "gw_polarizability_r",
            "gw_sphere_transform", "gw_polarizability", "gw_epsilon", "gw_eps_inverse", "gw_hpd_inverse",
            "gw_polarizability_batched", "gw_autotune", "gw_tail_init", "gw_tail_target", "gw_tail_features",
-           "gw_tail_forward", "gw_tail_train_step", "gw_tail_loss", "gw_tail_correct")
+           "gw_tail_forward", "gw_tail_train_step", "gw_tail_loss", "gw_tail_correct", "gw_newton_inverse",
+           "gw_eps_inverse_newton")
 TAIL_NWEIGHT, TAIL_NBIAS, TAIL_NPARAM = 21120, 289, 21409
 
 
@@ -92,6 +93,8 @@ def load() -> C.CDLL:
         "gw_tail_train_step": (i, [vp, C.POINTER(Mlp), C.POINTER(Adam), vp, vp, i, vp, vp]),
         "gw_tail_correct": (i, [vp, C.POINTER(Mlp), vp, i, vp, vp, C.POINTER(i), vp]),
         "gw_tail_loss": (i, [vp, C.POINTER(Mlp), vp, vp, i, vp, vp]),
+        "gw_newton_inverse": (i, [vp, vp, i, d, i, vp, C.POINTER(i), vp, vp]),
+        "gw_eps_inverse_newton": (i, [vp, vp, i, Grid, vp, vp, d, d, i, vp, C.POINTER(i), vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -333,6 +336,39 @@ def autotune(psi_v, psi_c, e_v, e_c, precision="bf16", p_scratch=None, ctx: Opti
     ctx.check(st, "gw_autotune")
     names = tile_names()
     return best.value, {names[t]: times[t] for t in range(ntile) if times[t] >= 0}
+
+
+def newton_inverse(a, tol=1e-11, max_iter=100, out=None, ctx: Optional[Context] = None):
+    """Inverse by the Newton iteration; returns (inverse, iterations, max-change history)."""
+    import torch
+    n = a.shape[0]
+    if out is None:
+        out = torch.empty_like(a)
+    ctx = ctx or context(a.device.index)
+    its = C.c_int(0)
+    hist = (C.c_double * max_iter)()
+    st = ctx.lib.gw_newton_inverse(ctx.handle, _dev(a, torch.complex128, "a"), n, float(tol), int(max_iter),
+                                   _dev(out, torch.complex128, "out"), C.byref(its), hist, _stream(a))
+    ctx.check(st, "gw_newton_inverse")
+    return out, its.value, [hist[i] for i in range(its.value)]
+
+
+def eps_inverse_newton(p_gg, n, a_bohr, q, miller, head=1.0, tol=1e-11, max_iter=100, out=None,
+                       ctx: Optional[Context] = None):
+    import torch
+    m, pm = _host_i32(miller, "g_miller")
+    ng = m.shape[0]
+    qa, pq = _host_f64(q, "q")
+    if out is None:
+        out = torch.empty((ng, ng), dtype=torch.complex128, device=p_gg.device)
+    ctx = ctx or context(p_gg.device.index)
+    its = C.c_int(0)
+    hist = (C.c_double * max_iter)()
+    st = ctx.lib.gw_eps_inverse_newton(ctx.handle, _dev(p_gg, torch.complex64, "p_gg"), ng, _grid(n, a_bohr), pq, pm,
+                                       float(head), float(tol), int(max_iter), _dev(out, torch.complex128, "eps_inv"),
+                                       C.byref(its), hist, _stream(p_gg))
+    ctx.check(st, "gw_eps_inverse_newton")
+    return out, its.value, [hist[i] for i in range(its.value)]
 
 
 def polarizability_batched(psi_v, e_v, n, a_bohr, jobs, precision="fp32", prefactor=1.0, tile=-1, head=1.0,

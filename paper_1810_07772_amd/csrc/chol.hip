@@ -267,4 +267,110 @@ hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small
   return hipGetLastError();
 }
 
+// ---- Newton iteration for the inverse (Sec. 5.1): X_{n+1} = X_n (2I - A X_n), X_0 = alpha A^H -------
+// alpha = 1 / max_i sum_j |(A A^H)_ij| (absolute values make alpha <= 1/sigma_max^2, so the iteration
+// converges for any nonsingular A).  Every product is the complex FP64 MFMA GEMM above.
+
+// per-row sum of |m_ij| into rs[i]
+__global__ void row_abs_sum_kernel(const double2 *__restrict__ m, int n, double *__restrict__ rs) {
+  const int i = blockIdx.x;
+  __shared__ double red[256];
+  double a = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double2 v = m[(size_t)i * n + j];
+    a += sqrt(v.x * v.x + v.y * v.y);
+  }
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rs[i] = red[0];
+}
+
+// out[0] = max of v[0..n) (one workgroup); with inv set, out[0] = 1 / max
+__global__ void max_reduce_kernel(const double *__restrict__ v, int n, double *__restrict__ out, int inv) {
+  __shared__ double red[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) a = fmax(a, v[i]);
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = inv ? 1.0 / red[0] : red[0];
+}
+
+// x = alpha * a^H with alpha read from device memory
+__global__ __launch_bounds__(256) void scaled_conj_transpose_kernel(const double2 *__restrict__ a, int n,
+                                                                    const double *__restrict__ alpha,
+                                                                    double2 *__restrict__ x) {
+  __shared__ double2 t[32][33];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const double al = alpha[0];
+  for (int k = 0; k < 32; k += 8) {
+    const int r = r0 + ty + k, c = c0 + tx;
+    if (r < n && c < n) t[ty + k][tx] = a[(size_t)r * n + c];
+  }
+  __syncthreads();
+  for (int k = 0; k < 32; k += 8) {
+    const int r = c0 + ty + k, c = r0 + tx;        // x[r][c] = alpha conj(a[c][r])
+    if (r < n && c < n) {
+      const double2 v = t[tx][ty + k];
+      x[(size_t)r * n + c] = make_double2(al * v.x, -al * v.y);
+    }
+  }
+}
+
+// per-row max |x_ij - y_ij| into rm[i]
+__global__ void row_max_diff_kernel(const double2 *__restrict__ x, const double2 *__restrict__ y, int n,
+                                    double *__restrict__ rm) {
+  const int i = blockIdx.x;
+  __shared__ double red[256];
+  double a = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double2 u = x[(size_t)i * n + j], v = y[(size_t)i * n + j];
+    const double dx = u.x - v.x, dy = u.y - v.y;
+    a = fmax(a, sqrt(dx * dx + dy * dy));
+  }
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rm[i] = red[0];
+}
+
+size_t newton_ws_bytes(int n) { return 3 * (size_t)n * n * sizeof(double2) + ((size_t)n + 64) * sizeof(double); }
+
+hipError_t newton_start(const double2 *a, int n, double2 *x, double2 *t, double *scratch, hipStream_t s) {
+  // t = A A^H, alpha = 1 / max_i sum_j |t_ij|, x = alpha A^H
+  GW_TRY(zgemm(n, n, n, a, n, 0, a, n, 1, t, n, 1.0, 0.0, 0, 0, s));
+  hipLaunchKernelGGL(row_abs_sum_kernel, dim3(n), dim3(256), 0, s, t, n, scratch + 64);
+  GW_TRY(hipGetLastError());
+  hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, scratch + 64, n, scratch, 1);
+  GW_TRY(hipGetLastError());
+  dim3 g((n + 31) / 32, (n + 31) / 32);
+  hipLaunchKernelGGL(scaled_conj_transpose_kernel, g, dim3(256), 0, s, a, n, scratch, x);
+  return hipGetLastError();
+}
+
+hipError_t newton_step(const double2 *a, int n, const double2 *x, double2 *t, double2 *xn, double *scratch,
+                       hipStream_t s) {
+  // t = 2I - A X, xn = X t, scratch[1] = max |xn - x|
+  const size_t nn = (size_t)n * n;
+  hipLaunchKernelGGL(fill_identity_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, t, n, 2.0);
+  GW_TRY(hipGetLastError());
+  GW_TRY(zgemm(n, n, n, a, n, 0, x, n, 0, t, n, -1.0, 1.0, 0, 0, s));
+  GW_TRY(zgemm(n, n, n, x, n, 0, t, n, 0, xn, n, 1.0, 0.0, 0, 0, s));
+  hipLaunchKernelGGL(row_max_diff_kernel, dim3(n), dim3(256), 0, s, xn, x, n, scratch + 64);
+  GW_TRY(hipGetLastError());
+  hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, scratch + 64, n, scratch + 1, 0);
+  return hipGetLastError();
+}
+
 }  // namespace gwi

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/gw.h: argument checks, workspace, planning of
 // the sphere transforms, and the launch sequences.  No device work is queued before every
 // argument check of a call has passed.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -523,6 +524,68 @@ int gw_hpd_inverse(gw_ctx *ctx, const gw_c64 *a, int n, gw_c64 *out, void *strea
   GW_STATUS(ws_get(ctx, WS_EPS, (size_t)n * n * sizeof(double2), &e, s));
   GW_HIP(ctx, hipMemcpyAsync(e, a, (size_t)n * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
   return hpd_inverse_impl(ctx, (double2 *)e, n, (double2 *)out, s);
+}
+
+int gw_newton_inverse(gw_ctx *ctx, const gw_c64 *a, int n, double tol, int max_iter, gw_c64 *out, int *iterations,
+                      double *history, void *stream) {
+  GW_STATUS(begin(ctx));
+  GW_CHECK(ctx, a && out && iterations, "a, out and iterations must not be NULL");
+  GW_CHECK(ctx, n > 0 && n <= 65536, "n must be in [1, 65536]");
+  GW_CHECK(ctx, std::isfinite(tol) && tol > 0.0, "tol must be positive");
+  GW_CHECK(ctx, max_iter > 0 && max_iter <= 10000, "max_iter must be in [1, 10000]");
+  if (ctx->device < 0) { *iterations = 0; return GW_OK; }
+  hipStream_t s = as_stream(stream);
+  void *w;
+  GW_STATUS(ws_get(ctx, WS_NEWTON, newton_ws_bytes(n), &w, s));
+  const size_t nn = (size_t)n * n;
+  double2 *x = (double2 *)w, *t = x + nn, *xn = t + nn;
+  double *sc = (double *)(xn + nn);
+  GW_HIP(ctx, newton_start((const double2 *)a, n, x, t, sc, s));
+  double *host = (double *)ctx->pivot_host;     // pinned scratch (8 bytes are enough for one double)
+  (void)host;
+  double diff = 0.0;
+  int it = 0;
+  for (it = 1; it <= max_iter; ++it) {
+    GW_HIP(ctx, newton_step((const double2 *)a, n, x, t, xn, sc, s));
+    GW_HIP(ctx, hipMemcpyAsync(&diff, sc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    GW_HIP(ctx, hipStreamSynchronize(s));
+    if (history) history[it - 1] = diff;
+    std::swap(x, xn);
+    if (!(diff >= tol)) break;     // converged (or NaN: stop and report)
+  }
+  *iterations = std::min(it, max_iter);
+  GW_HIP(ctx, hipMemcpyAsync(out, x, nn * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  GW_HIP(ctx, hipStreamSynchronize(s));
+  if (!std::isfinite(diff)) {
+    set_err(ctx, "Newton iteration diverged (max change is not finite)");
+    return GW_E_NOTPD;
+  }
+  if (diff >= tol) {
+    set_err(ctx, "Newton iteration did not reach tol %.3g in %d iterations (last max change %.3g)", tol, max_iter,
+            diff);
+    return GW_E_UNSUPPORTED;
+  }
+  return GW_OK;
+}
+
+int gw_eps_inverse_newton(gw_ctx *ctx, const gw_c32 *p_gg, int ng, gw_grid grid, const double *q, const int *g_miller,
+                          double head, double tol, int max_iter, gw_c64 *eps_inv, int *iterations, double *history,
+                          void *stream) {
+  GW_STATUS(begin(ctx));
+  GW_CHECK(ctx, p_gg && eps_inv && iterations, "p_gg, eps_inv and iterations must not be NULL");
+  GW_CHECK(ctx, q != nullptr, "q must not be NULL");
+  GW_STATUS(check_grid(ctx, grid));
+  GW_STATUS(check_sphere(ctx, grid, g_miller, ng));
+  if (std::isnan(head)) head = 1.0;
+  GW_CHECK(ctx, std::isfinite(head) && head > 0.0, "head must be positive");
+  GW_CHECK(ctx, std::isfinite(tol) && tol > 0.0, "tol must be positive");
+  GW_CHECK(ctx, max_iter > 0 && max_iter <= 10000, "max_iter must be in [1, 10000]");
+  if (ctx->device < 0) { *iterations = 0; return GW_OK; }
+  hipStream_t s = as_stream(stream);
+  void *e;
+  GW_STATUS(ws_get(ctx, WS_EPS, (size_t)ng * ng * sizeof(double2), &e, s));
+  GW_STATUS(eps_build_impl(ctx, (const float2 *)p_gg, ng, grid, q, g_miller, head, (double2 *)e, s));
+  return gw_newton_inverse(ctx, (const gw_c64 *)e, ng, tol, max_iter, eps_inv, iterations, history, stream);
 }
 
 }  // extern "C"

@@ -45,6 +45,7 @@ enum SlotId {
   WS_PGG_T,       // complex64 [ng][ng] transposed sphere result
   WS_TAIL,        // learned-tail intermediates
   WS_TAIL_FLAG,   // training-box flag
+  WS_NEWTON,      // Newton iteration buffers
   WS_COUNT_BASE
 };
 
@@ -87,6 +88,11 @@ size_t chol_small_bytes(int n);
 hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small, int *pivot_dev, double2 *out,
                        hipStream_t s);
 hipError_t launch_fill_int(int *p, int value, hipStream_t s);
+// Newton iteration for the inverse: workspace of newton_ws_bytes(n) holds x, t, xn and the scalars.
+size_t newton_ws_bytes(int n);
+hipError_t newton_start(const double2 *a, int n, double2 *x, double2 *t, double *scratch, hipStream_t s);
+hipError_t newton_step(const double2 *a, int n, const double2 *x, double2 *t, double2 *xn, double *scratch,
+                       hipStream_t s);
 
 // Learned band-tail correction (tail.hip).
 size_t tail_ws_floats(int n);

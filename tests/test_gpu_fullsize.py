@@ -64,3 +64,9 @@ def test_production_size(setup, prec, tol):
     # separately, so they may differ at the rounding level of the precision
     assert herm <= 0.1 * tol
     assert e_inv < 1e-10
+    if prec == "fp32":
+        # the paper's Newton iteration on the same P~, at N_g = 4067
+        xn, it, hist = gw.eps_inverse_newton(pgg, s.n, s.a_bohr, s.q, s.miller, tol=1e-11)
+        e_n = orc.rel_f(xn.cpu().numpy(), ei_ref)
+        print(f"Newton at N_g = {len(s.miller)}: {it} iterations, last change {hist[-1]:.1e}, rel_F vs LU {e_n:.2e}")
+        assert hist[-1] < 1e-11 and e_n < 1e-10
