@@ -14,7 +14,9 @@ Conventions (shared input format, stated once):
 * Orbitals are grid-normalised: sum_r |psi_n(r)|^2 = 1, with
   psi_n(r) = N_r^(-1/2) sum_m c_nm exp(+i 2pi m.i/n), i.e. the plane-wave to
   real-space transform of the paper's Sec. 4.1 (periodic parts u_nk built from
-  their plane-wave coefficients) written on the grid.
+  their plane-wave coefficients) written on the grid.  Grid orbitals handed
+  out here come from numpy's inverse FFT of the drawn coefficients; systems also
+  carry the coefficients themselves, for the library's own transform of them.
 * Energies are returned in Hartree.
 * Cubic cell of side a = 0.855 * n Bohr, Omega = a^3 (the paper gives no cell
   size; this makes a 12^3 grid a 10.26 Bohr cell, close to bulk Si).
@@ -75,14 +77,15 @@ def cell_side(n: int) -> float:
 # ---------------------------------------------------------------------------
 # Orbitals and energies
 # ---------------------------------------------------------------------------
-def orbitals(rng: np.random.Generator, n: Sequence[int], r2_psi: float, nbands: int) -> np.ndarray:
-    """Grid-orthonormal random orbitals, complex128 [nbands][N_r].
+def orbital_coefficients(rng: np.random.Generator, n: Sequence[int], r2_psi: float,
+                         nbands: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Orthonormal random plane-wave coefficients on the sphere |m|^2 <= r2_psi.
 
-    Draw order: real parts then imaginary parts of the coefficient block
+    Returns (Miller list int32 [N_pw][3] in sphere order, coefficients complex128
+    [nbands][N_pw]).  Draw order: real parts then imaginary parts of the block
     [N_pw][nbands] (standard normal, /sqrt(2)), Gaussian envelope
     exp(-|m|^2 / r2_psi) (sigma^2 = r2_psi/2), reduced QR with the phase of
-    diag(R) removed so diag(R) > 0, then the coefficients are placed on the
-    grid and transformed with numpy's inverse FFT times sqrt(N_r).
+    diag(R) removed so diag(R) > 0.
     """
     n = tuple(int(x) for x in n)
     mp = sphere(n, r2=r2_psi)
@@ -97,11 +100,25 @@ def orbitals(rng: np.random.Generator, n: Sequence[int], r2_psi: float, nbands: 
     qm, rm = np.linalg.qr(c, mode="reduced")
     d = np.diag(rm)
     qm = qm * (d / np.abs(d))[None, :]
+    return mp, np.ascontiguousarray(qm.T)
+
+
+def coefficients_on_grid(n: Sequence[int], mp: np.ndarray, coeff: np.ndarray) -> np.ndarray:
+    """Grid orbitals from plane-wave coefficients by numpy's inverse FFT times sqrt(N_r)
+    (the input convention above), complex128 [nbands][N_r]."""
+    n = tuple(int(x) for x in n)
     nr = n[0] * n[1] * n[2]
-    box = np.zeros((nbands,) + n, dtype=np.complex128)
-    box[:, mp[:, 0] % n[0], mp[:, 1] % n[1], mp[:, 2] % n[2]] = qm.T
+    box = np.zeros((coeff.shape[0],) + n, dtype=np.complex128)
+    box[:, mp[:, 0] % n[0], mp[:, 1] % n[1], mp[:, 2] % n[2]] = coeff
     psi = np.fft.ifftn(box, axes=(1, 2, 3)) * np.sqrt(nr)
-    return np.ascontiguousarray(psi.reshape(nbands, nr))
+    return np.ascontiguousarray(psi.reshape(coeff.shape[0], nr))
+
+
+def orbitals(rng: np.random.Generator, n: Sequence[int], r2_psi: float, nbands: int) -> np.ndarray:
+    """Grid-orthonormal random orbitals, complex128 [nbands][N_r]: the coefficients of
+    orbital_coefficients placed on the grid by coefficients_on_grid."""
+    mp, c = orbital_coefficients(rng, n, r2_psi, nbands)
+    return coefficients_on_grid(n, mp, c)
 
 
 def energies(rng: np.random.Generator, nv: int, nc: int) -> Tuple[np.ndarray, np.ndarray]:
@@ -143,6 +160,8 @@ class System:
     q: np.ndarray              # float64 [3], crystal units
     miller: np.ndarray         # int32 [ng][3], ordered sphere
     meta: dict = field(default_factory=dict)
+    pw_miller: Optional[np.ndarray] = None   # int32 [npw][3], the orbitals' plane-wave sphere
+    coeff: Optional[np.ndarray] = None       # complex128 [nv + nc][npw], occupied bands first
 
     @property
     def nr(self) -> int:
@@ -173,11 +192,12 @@ def make_system(n: int, nv: int, nc: int, r2_psi: float, r2_p: Optional[float] =
     """One seeded system: bands 0..nv-1 of the QR'd set are occupied, nv..nv+nc-1 unoccupied."""
     rng = np.random.default_rng(seed)
     grid = (n, n, n)
-    psi = orbitals(rng, grid, r2_psi, nv + nc)
+    mp, coeff = orbital_coefficients(rng, grid, r2_psi, nv + nc)
+    psi = coefficients_on_grid(grid, mp, coeff)
     ev, ec = energies(rng, nv, nc)
     mill = sphere(grid, r2=(r2_psi if r2_p is None else r2_p), q=q, count=ng)
     return System(grid, cell_side(n), psi[:nv].copy(), psi[nv:].copy(), ev, ec,
-                  np.asarray(q, dtype=np.float64), mill, {"seed": seed, "r2_psi": r2_psi})
+                  np.asarray(q, dtype=np.float64), mill, {"seed": seed, "r2_psi": r2_psi}, mp, coeff)
 
 
 def truncate(sys_: System, nc: int) -> System:

@@ -31,7 +31,7 @@ import numpy as np
 __all__ = [
     "pair_products", "polarizability_r", "row_transform", "to_sphere", "coulomb_sqrt",
     "epsilon", "eps_inverse", "eps_inverse_cholesky", "newton_schulz_inverse", "adler_wiser",
-    "rel_f", "grid_phase_index", "adler_wiser_selected",
+    "rel_f", "grid_phase_index", "adler_wiser_selected", "orbitals_on_grid",
 ]
 
 
@@ -47,6 +47,21 @@ def _scales(e_v, e_c, prefactor):
     if np.any(de <= 0):
         raise ValueError("every E_c - E_v must be positive")
     return np.sqrt(prefactor / de)
+
+
+def orbitals_on_grid(coeff, miller, n: Sequence[int], points=None) -> np.ndarray:
+    """Sec. 4.1, the step from plane-wave coefficients to the orbitals' periodic parts on the
+    real-space grid (Table 1's first row), as the direct sum
+        psi_n(r) = N_r^(-1/2) sum_m c_nm exp(+2 pi i (m1 i1/n1 + m2 i2/n2 + m3 i3/n3)),
+    r = (i1*n2 + i2)*n3 + i3.  coeff complex [nb][npw], miller int [npw][3].  Returns
+    complex128 [nb][N_r], or [nb][len(points)] for the grid indices in `points`."""
+    n = tuple(int(x) for x in n)
+    nr = n[0] * n[1] * n[2]
+    r = np.arange(nr) if points is None else np.asarray(points, np.int64)
+    i1, i2, i3 = r // (n[1] * n[2]), (r // n[2]) % n[1], r % n[2]
+    m = np.asarray(miller, np.float64)
+    phase = (np.outer(m[:, 0], i1) / n[0] + np.outer(m[:, 1], i2) / n[1] + np.outer(m[:, 2], i3) / n[2])
+    return np.asarray(coeff, np.complex128) @ np.exp(2j * np.pi * phase) / np.sqrt(nr)
 
 
 def pair_products(psi_v, psi_c, e_v, e_c, prefactor: float = 1.0) -> np.ndarray:

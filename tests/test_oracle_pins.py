@@ -305,3 +305,43 @@ def test_sphere_order_and_count_rule():
     d2 = ((m + np.array(q)) ** 2).sum(axis=1)
     assert len(m) == 2500 and np.all(np.diff(d2) >= 0)
     assert len({tuple(x) for x in m}) == 2500
+
+
+def test_orbitals_on_grid_hand_values():
+    """One plane wave m = (1, 0, 0) on a 4^3 grid: psi(i1, i2, i3) = i^{i1} / 8 (exp(+i pi/2 i1) / sqrt(64))."""
+    c = np.array([[1.0 + 0j]])
+    psi = orc.orbitals_on_grid(c, np.array([[1, 0, 0]]), (4, 4, 4))[0]
+    assert abs(psi[0] - 1 / 8) < 1e-16
+    assert abs(psi[16] - 1j / 8) < 1e-16           # r = (1, 0, 0)
+    assert abs(psi[32] + 1 / 8) < 1e-16            # r = (2, 0, 0)
+    assert abs(psi[1] - 1 / 8) < 1e-16             # r = (0, 0, 1): m3 = 0, no phase
+    # m = (0, 1, -1) on 4 x 5 x 6, r = (0, 2, 3): exp(2 pi i (2/5 - 3/6)) / sqrt(120)
+    psi = orc.orbitals_on_grid(c, np.array([[0, 1, -1]]), (4, 5, 6), points=[2 * 6 + 3])[0, 0]
+    assert abs(psi - np.exp(2j * np.pi * (0.4 - 0.5)) / np.sqrt(120)) < 1e-15
+
+
+def test_orbitals_on_grid_equals_inverse_fft_on_a_non_cubic_grid():
+    """Special case that reduces to a library routine: numpy's inverse FFT times sqrt(N_r); the
+    6 x 5 x 4 grid catches a swapped axis, and the sign of the exponent a conjugation."""
+    n = (6, 5, 4)
+    rng = np.random.default_rng(3)
+    mp = gs.sphere(n, r2=3.0)
+    c = rng.standard_normal((3, len(mp))) + 1j * rng.standard_normal((3, len(mp)))
+    box = np.zeros((3,) + n, dtype=np.complex128)
+    for j, m in enumerate(mp):
+        box[:, m[0] % n[0], m[1] % n[1], m[2] % n[2]] = c[:, j]
+    ref = np.fft.ifftn(box, axes=(1, 2, 3)).reshape(3, -1) * np.sqrt(120)
+    got = orc.orbitals_on_grid(c, mp, n)
+    assert np.max(np.abs(got - ref)) < 1e-14
+    # sampled points equal the full transform's columns
+    pts = [0, 7, 119]
+    assert np.max(np.abs(orc.orbitals_on_grid(c, mp, n, points=pts) - got[:, pts])) < 1e-15
+
+
+def test_orbitals_on_grid_orthonormal_and_equal_to_generator():
+    """Orthonormal coefficient vectors give grid-orthonormal orbitals (Parseval), and the
+    direct sum equals the generator's numpy-FFT orbitals for the same draws."""
+    s = gs.make_system(8, 4, 12, r2_psi=6.0, seed=5)
+    psi = orc.orbitals_on_grid(s.coeff, s.pw_miller, s.n)
+    assert np.max(np.abs(psi @ psi.conj().T - np.eye(16))) < 1e-13
+    assert np.max(np.abs(psi[:4] - s.psi_v)) < 1e-14 and np.max(np.abs(psi[4:] - s.psi_c)) < 1e-14
