@@ -234,6 +234,29 @@ def main():
         log(f"pair products: {t * 1e3:.2f} ms, {nbytes / t / 1e9:.0f} GB/s")
         del f
 
+    # orbitals from their plane-wave coefficients (the step before the pair products), all bands
+    orb = None
+    if s.coeff is not None:
+        cf = torch.from_numpy(s.coeff.astype(np.complex64)).to(dev)
+        psi_all = torch.empty((nv + nc, nr), dtype=torch.complex64, device=dev)
+        gw.orbitals_to_grid(cf, s.n, s.pw_miller, out=psi_all)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record(stream)
+        for _ in range(reps):
+            gw.orbitals_to_grid(cf, s.n, s.pw_miller, out=psi_all)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / reps
+        npw = s.pw_miller.shape[0]
+        nbytes = 8.0 * (nv + nc) * (npw + nr)          # read the coefficients, write the orbitals
+        orb = {"bound": "hbm", "achieved": round(nbytes / t / 1e9, 1), "peak": HBM_GBS, "unit": "GB/s",
+               "frac": round(nbytes / t / 1e9 / HBM_GBS, 4), "ms": round(t * 1e3, 3),
+               "unit_work": f"{nv + nc} bands x {npw} plane waves -> {nr} points",
+               "max_abs_vs_host_orbitals": float((psi_all[:nv] - pv).abs().max().item())}
+        log(f"orbitals to grid: {t * 1e3:.2f} ms, {nbytes / t / 1e9:.0f} GB/s")
+        del cf, psi_all
+
     # eps^-1 two ways at N_g: the FP64 Cholesky route the step times (about 4 N_g^3 flops) and the
     # Newton iteration of Sec. 5.1 (8 N_g^3 for A A^H, then 16 N_g^3 per iteration), both on FP64 MFMA
     chol = {"bound": "mfma", "achieved": round(4.0 * ng ** 3 / head["eps_inverse_s"] / 1e12, 2),
@@ -306,6 +329,7 @@ def main():
         "transforms_roofline": {"bound": "hbm", "achieved": round(head["transforms_gbs"], 1), "peak": HBM_GBS,
                                 "unit": "GB/s", "frac": round(head["transforms_gbs"] / HBM_GBS, 4)},
         "pair_products_roofline": pp,
+        "orbitals_roofline": orb,
         "eps_inverse_cholesky_roofline": chol,
         "eps_inverse_newton": newton,
     }

@@ -104,6 +104,21 @@ const char *gw_tile_name(int tile);
 int gw_default_tile(int precision, int nr);
 
 /* ---------------------------------------------------------------------------
+ * Orbitals on the grid from their plane-wave coefficients (Sec. 4.1, the
+ * transform of the wavefunctions to real space that precedes the pair
+ * products; Table 1's first row):
+ *   psi[n][r] = N_r^(-1/2) sum_m coeff[n][m] exp(+2 pi i (m1 i1/n1 + m2 i2/n2 + m3 i3/n3)),
+ *   r = (i1*n2 + i2)*n3 + i3, so grid-orthonormal orbitals come from orthonormal
+ *   coefficient vectors.
+ *   coeff [nb][npw] complex64 (device, read only); pw_miller host [npw][3]
+ *   distinct Miller triples with |m_d| < n_d/2; psi [nb][N_r] complex64
+ *   (device), written entirely.  FP32 transform: three pruned 1-D passes.
+ *   Grid sides as for gw_sphere_transform (else GW_E_UNSUPPORTED).
+ * ------------------------------------------------------------------------- */
+int gw_orbitals_to_grid(gw_ctx *ctx, const gw_c32 *coeff, int nb, int npw, gw_grid grid, const int *pw_miller,
+                        gw_c32 *psi, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Pair products, Eq.(fdef):  f_out[v*nc + c][r] = conj(psi_v[v][r]) psi_c[c][r] sqrt(p/(E_c - E_v)).
  *   psi_v [nv][nr], psi_c [nc][nr] complex64; e_v[nv], e_c[nc] (host, Hartree);
  *   f_out [nv*nc][nr] complex64, written entirely.  FP32 product of the FP32

@@ -5,4 +5,5 @@ package only marshals arguments to it.  There is no CPU fallback: if the library
 built, every entry point raises."""
 from ._lib import (GwError, Context, context, load, tile_names, default_tile_name, pair_products, polarizability_r,  # noqa: F401
                    sphere_transform, polarizability, epsilon, eps_inverse, hpd_inverse, polarizability_batched, autotune,
-                   EXPORTS, LIB_PATH, TailModel, tail_target, tail_features, newton_inverse, eps_inverse_newton)
+                   EXPORTS, LIB_PATH, TailModel, tail_target, tail_features, newton_inverse, eps_inverse_newton,
+                   orbitals_to_grid)

@@ -22,7 +22,7 @@ EXPORTS = ("gw_opts_default", "gw_version", "gw_status_string", "gw_create", "gw
            "gw_sphere_transform", "gw_polarizability", "gw_epsilon", "gw_eps_inverse", "gw_hpd_inverse",
            "gw_polarizability_batched", "gw_autotune", "gw_tail_init", "gw_tail_target", "gw_tail_features",
            "gw_tail_forward", "gw_tail_train_step", "gw_tail_loss", "gw_tail_correct", "gw_newton_inverse",
-           "gw_eps_inverse_newton")
+           "gw_eps_inverse_newton", "gw_orbitals_to_grid")
 TAIL_NWEIGHT, TAIL_NBIAS, TAIL_NPARAM = 21120, 289, 21409
 
 
@@ -93,6 +93,7 @@ def load() -> C.CDLL:
         "gw_tail_train_step": (i, [vp, C.POINTER(Mlp), C.POINTER(Adam), vp, vp, i, vp, vp]),
         "gw_tail_correct": (i, [vp, C.POINTER(Mlp), vp, i, vp, vp, C.POINTER(i), vp]),
         "gw_tail_loss": (i, [vp, C.POINTER(Mlp), vp, vp, i, vp, vp]),
+        "gw_orbitals_to_grid": (i, [vp, vp, i, i, Grid, vp, vp, vp]),
         "gw_newton_inverse": (i, [vp, vp, i, d, i, vp, C.POINTER(i), vp, vp]),
         "gw_eps_inverse_newton": (i, [vp, vp, i, Grid, vp, vp, d, d, i, vp, C.POINTER(i), vp, vp]),
     }
@@ -336,6 +337,24 @@ def autotune(psi_v, psi_c, e_v, e_c, precision="bf16", p_scratch=None, ctx: Opti
     ctx.check(st, "gw_autotune")
     names = tile_names()
     return best.value, {names[t]: times[t] for t in range(ntile) if times[t] >= 0}
+
+
+def orbitals_to_grid(coeff, n, pw_miller, out=None, ctx: Optional[Context] = None):
+    """psi [nb][N_r] complex64 on the grid from plane-wave coefficients [nb][npw] on the device."""
+    import torch
+    m, pm = _host_i32(pw_miller, "pw_miller")
+    nb, npw = coeff.shape
+    if m.shape[0] != npw:
+        raise ValueError(f"pw_miller has {m.shape[0]} rows for {npw} coefficients")
+    nt = tuple(int(x) for x in (n if np.ndim(n) else (n, n, n)))
+    nr = nt[0] * nt[1] * nt[2]
+    if out is None:
+        out = torch.empty((nb, nr), dtype=torch.complex64, device=coeff.device)
+    ctx = ctx or context(coeff.device.index)
+    st = ctx.lib.gw_orbitals_to_grid(ctx.handle, _dev(coeff, torch.complex64, "coeff"), nb, npw, _grid(nt, 1.0), pm,
+                                     _dev(out, torch.complex64, "psi"), _stream(coeff))
+    ctx.check(st, "gw_orbitals_to_grid")
+    return out
 
 
 def newton_inverse(a, tol=1e-11, max_iter=100, out=None, ctx: Optional[Context] = None):

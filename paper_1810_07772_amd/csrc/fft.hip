@@ -167,6 +167,36 @@ __global__ __launch_bounds__(FFT_THREADS) void fft_pass_kernel(const float2 *__r
   }
 }
 
+// The adjoint of the pass above: input rows are gathered through a map (-1 reads zero), the N
+// outputs go to rows (o*N + k)*U + u.  With the sphere plan's maps this runs a transform from
+// the sphere to the full grid (plane-wave coefficients to orbitals), axis by axis in reverse.
+template <int N, int SIGN>
+__global__ __launch_bounds__(FFT_THREADS) void fft_gather_pass_kernel(const float2 *__restrict__ in,
+                                                                       float2 *__restrict__ out, int U, int B,
+                                                                       long long ld_in, long long ld_out,
+                                                                       const int *__restrict__ map, float scale) {
+  const int b = blockIdx.x * FFT_THREADS + threadIdx.x;
+  if (b >= B) return;
+  const int ou = blockIdx.y;
+  const int o = ou / U, u = ou - o * U;
+  const int *mrow = map + (size_t)ou * N;
+  float2 x[N], X[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int row = mrow[i];
+    float2 v = make_float2(0.f, 0.f);
+    if (row >= 0) {
+      v = in[(long long)row * ld_in + b];
+      v.x *= scale;
+      v.y *= scale;
+    }
+    x[i] = v;
+  }
+  dft_regs<N, SIGN>(x, X);
+#pragma unroll
+  for (int k = 0; k < N; ++k) out[((long long)(o * N + k) * U + u) * ld_out + b] = X[k];
+}
+
 #define GW_FFT_SIZES(X) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16) X(18) X(20) X(24) X(27) X(30) X(32) X(36) X(40) X(48)
 
 bool fft_size_supported(int n) {
@@ -193,6 +223,27 @@ hipError_t launch_fft_pass(int n, int sign, const float2 *in, float2 *out, int O
     else                                                                                                     \
       hipLaunchKernelGGL(HIP_KERNEL_NAME(fft_pass_kernel<n_, 1>), grid, block, 0, s, in, out, U, B, ld_in,  \
                          ld_out, map);                                                                       \
+    break;
+    GW_FFT_SIZES(GW_CASE)
+#undef GW_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_gather_pass(int n, int sign, const float2 *in, float2 *out, int O, int U, int B, long long ld_in,
+                                  long long ld_out, const int *map, float scale, hipStream_t s) {
+  dim3 grid((B + FFT_THREADS - 1) / FFT_THREADS, O * U), block(FFT_THREADS);
+  if ((long long)O * U > 65535) return hipErrorInvalidValue;
+  switch (n) {
+#define GW_CASE(n_)                                                                                            \
+  case n_:                                                                                                     \
+    if (sign < 0)                                                                                              \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(fft_gather_pass_kernel<n_, -1>), grid, block, 0, s, in, out, U, B,   \
+                         ld_in, ld_out, map, scale);                                                           \
+    else                                                                                                       \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(fft_gather_pass_kernel<n_, 1>), grid, block, 0, s, in, out, U, B,    \
+                         ld_in, ld_out, map, scale);                                                           \
     break;
     GW_FFT_SIZES(GW_CASE)
 #undef GW_CASE

@@ -451,6 +451,51 @@ int gw_sphere_transform(gw_ctx *ctx, const gw_c32 *p_rr, gw_grid grid, const int
   return sphere_transform_impl(ctx, (const float2 *)p_rr, grid, g_miller, ng, (float2 *)p_gg, as_stream(stream));
 }
 
+int gw_orbitals_to_grid(gw_ctx *ctx, const gw_c32 *coeff, int nb, int npw, gw_grid grid, const int *pw_miller,
+                        gw_c32 *psi, void *stream) {
+  GW_STATUS(begin(ctx));
+  GW_CHECK(ctx, coeff && psi, "coeff and psi must not be NULL");
+  GW_CHECK(ctx, nb > 0, "nb must be positive (got %d)", nb);
+  GW_STATUS(check_grid(ctx, grid));
+  const long long nrl = (long long)grid.n1 * grid.n2 * grid.n3;
+  GW_CHECK(ctx, nrl <= (1 << 24), "grid too large");
+  GW_STATUS(check_sphere(ctx, grid, pw_miller, npw));
+  GW_STATUS(grid_supported(ctx, grid));
+  if (ctx->device < 0) return GW_OK;
+  hipStream_t s = as_stream(stream);
+  const int nr = (int)nrl;
+  SpherePlan p;
+  build_sphere_plan(grid, pw_miller, npw, p);
+  // band chunk: the largest intermediate ([nr][w]) stays near 1 GiB
+  const int w = (int)std::min<long long>(nb, std::max<long long>(64, (1LL << 27) / nr));
+  const size_t rows1 = (size_t)p.n1 * p.n2 * p.m3count, rows2 = (size_t)p.n1 * p.npair;
+  void *ct, *a1, *a2, *rt, *maps;
+  GW_STATUS(ws_get(ctx, WS_ORB_T, (size_t)npw * w * sizeof(float2), &ct, s));
+  GW_STATUS(ws_get(ctx, WS_ORB_A1, rows1 * w * sizeof(float2), &a1, s));
+  GW_STATUS(ws_get(ctx, WS_ORB_A2, rows2 * w * sizeof(float2), &a2, s));
+  GW_STATUS(ws_get(ctx, WS_ORB_R, (size_t)nr * w * sizeof(float2), &rt, s));
+  const size_t nA = p.mapA.size(), nB = p.mapB.size(), nC = p.mapC.size();
+  GW_STATUS(ws_get(ctx, WS_ORB_MAP, (nA + nB + nC) * sizeof(int), &maps, s));
+  int *dA = (int *)maps, *dB = dA + nA, *dC = dB + nB;
+  GW_HIP(ctx, hipMemcpyAsync(dA, p.mapA.data(), nA * sizeof(int), hipMemcpyHostToDevice, s));
+  GW_HIP(ctx, hipMemcpyAsync(dB, p.mapB.data(), nB * sizeof(int), hipMemcpyHostToDevice, s));
+  GW_HIP(ctx, hipMemcpyAsync(dC, p.mapC.data(), nC * sizeof(int), hipMemcpyHostToDevice, s));
+  const float scale = (float)(1.0 / std::sqrt((double)nr));
+  const float2 *c = (const float2 *)coeff;
+  float2 *out = (float2 *)psi;
+  for (int b0 = 0; b0 < nb; b0 += w) {
+    const int bw = std::min(w, nb - b0);
+    float2 *t = (float2 *)ct, *x1 = (float2 *)a1, *x2 = (float2 *)a2, *r = (float2 *)rt;
+    GW_HIP(ctx, launch_transpose_c64(c + (size_t)b0 * npw, t, bw, npw, npw, bw, s));
+    // sphere -> (i1, pair) along axis 1; -> (i1, i2, m3) along axis 2; -> grid along axis 3
+    GW_HIP(ctx, launch_fft_gather_pass(p.n1, +1, t, x2, 1, p.npair, bw, bw, bw, dC, scale, s));
+    GW_HIP(ctx, launch_fft_gather_pass(p.n2, +1, x2, x1, p.n1, p.m3count, bw, bw, bw, dB, 1.0f, s));
+    GW_HIP(ctx, launch_fft_gather_pass(p.n3, +1, x1, r, p.n1 * p.n2, 1, bw, bw, bw, dA, 1.0f, s));
+    GW_HIP(ctx, launch_transpose_c64(r, out + (size_t)b0 * nr, nr, bw, bw, nr, s));
+  }
+  return GW_OK;
+}
+
 int gw_polarizability(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const gw_c32 *psi_unocc, int nc, const double *e_v,
                       const double *e_c, gw_grid grid, const double *q, const int *g_miller, int ng,
                       const gw_opts *opts, gw_c32 *p_rr, gw_c32 *p_gg, void *stream) {

@@ -136,6 +136,25 @@ def test_dry_run_other_entry_points(gw):
     assert lib.gw_hpd_inverse(h, vp(), 10, vp(), None) == 0
     assert lib.gw_create(None, 0, 0) == 1
     assert lib.gw_destroy(None) == 1
+    # plane-wave coefficients to the grid
+    assert lib.gw_orbitals_to_grid(h, vp(), 3, len(m), grid, pm, vp(), None) == 0
+    assert lib.gw_orbitals_to_grid(h, vp(), 0, len(m), grid, pm, vp(), None) == 1
+    assert lib.gw_orbitals_to_grid(h, vp(0), 3, len(m), grid, pm, vp(), None) == 1
+    assert lib.gw_orbitals_to_grid(h, vp(), 3, 0, grid, pm, vp(), None) == 1
+    dup = m.copy(); dup[1] = dup[0]
+    assert lib.gw_orbitals_to_grid(h, vp(), 3, len(m), grid, i32(dup)[1], vp(), None) == 1
+    m7, pm7 = i32(gs.sphere((7, 7, 7), r2=2.0))
+    assert lib.gw_orbitals_to_grid(h, vp(), 3, len(m7), gw._lib.Grid(7, 7, 7, 6.0), pm7, vp(), None) == 5
+    # Newton iteration arguments
+    its = C.c_int(-1)
+    assert lib.gw_newton_inverse(h, vp(), 10, 1e-11, 50, vp(), C.byref(its), None, None) == 0 and its.value == 0
+    assert lib.gw_newton_inverse(h, vp(), 10, 0.0, 50, vp(), C.byref(its), None, None) == 1
+    assert lib.gw_newton_inverse(h, vp(), 10, 1e-11, 0, vp(), C.byref(its), None, None) == 1
+    assert lib.gw_newton_inverse(h, vp(), 0, 1e-11, 50, vp(), C.byref(its), None, None) == 1
+    assert lib.gw_eps_inverse_newton(h, vp(), len(m), grid, pq, pm, 1.0, 1e-11, 50, vp(), C.byref(its), None,
+                                     None) == 0
+    assert lib.gw_eps_inverse_newton(h, vp(), len(m), grid, pq, pm, 1.0, float("nan"), 50, vp(), C.byref(its), None,
+                                     None) == 1
 
 
 def test_product_path_has_no_fallback(gw, monkeypatch):

@@ -1,0 +1,97 @@
+"""GPU parity of the plane-wave to grid transform of the orbitals (Sec. 4.1, Table 1's first row)
+against the oracle's direct sum: small cubic and non-cubic grids, the production 36^3 orbital set
+(1152 bands, sampled points), a band count that needs two chunks, single-coefficient edge cases,
+and the transform feeding the polarizability build."""
+import numpy as np
+import pytest
+
+import gwsynth as gs
+import oracle as orc
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1810_07772_amd as gw
+    gw.load()
+    return gw
+
+
+def c64(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x).astype(np.complex64))).to("cuda:0")
+
+
+@pytest.mark.parametrize("n,r2,nb", [((8, 8, 8), 6.0, 16), ((12, 10, 9), 8.0, 37), ((16, 16, 16), 20.0, 300)])
+def test_small_grids_full(gw, n, r2, nb):
+    # FP32 transform: about a dozen roundings of 6e-8 per output, so 1e-6 relative
+    rng = np.random.default_rng(sum(n))
+    mp = gs.sphere(n, r2=r2)
+    c = (rng.standard_normal((nb, len(mp))) + 1j * rng.standard_normal((nb, len(mp)))).astype(np.complex64)
+    psi = gw.orbitals_to_grid(c64(c), n, mp).cpu().numpy()
+    ref = orc.orbitals_on_grid(c.astype(np.complex128), mp, n)
+    e = orc.rel_f(psi, ref)
+    print(f"{n} npw={len(mp)} nb={nb}: rel_F {e:.2e}")
+    assert e < 1e-6
+
+
+def test_production_orbitals_36(gw):
+    """The 36^3 set of the full-size build: 128 + 1024 bands on the 4067-vector sphere."""
+    s = gs.make_system(36, 128, 1024, r2_psi=98.0, seed=0)
+    c = s.coeff.astype(np.complex64)
+    psi = gw.orbitals_to_grid(c64(c), s.n, s.pw_miller)
+    torch.cuda.synchronize()
+    pts = np.array([0, 1, 35, 1296, 23328, 46655])
+    got = psi[:, torch.from_numpy(pts).to(psi.device)].cpu().numpy()
+    ref = orc.orbitals_on_grid(c.astype(np.complex128), s.pw_miller, s.n, points=pts)
+    e_pts = orc.rel_f(got, ref)
+    # the whole set against the generator's numpy FFT of the same coefficients
+    full = psi.cpu().numpy()
+    e_all = orc.rel_f(full, np.concatenate([s.psi_v, s.psi_c]))
+    g = full[:64].astype(np.complex128)                  # the Gram matrix in FP64 on the host
+    ortho = float(np.max(np.abs(g @ g.conj().T - np.eye(64))))
+    print(f"36^3: sampled points rel_F {e_pts:.2e}, whole set vs numpy {e_all:.2e}, orthonormality {ortho:.1e}")
+    assert e_pts < 1e-6 and e_all < 1e-6 and ortho < 1e-6
+
+
+def test_two_band_chunks_48(gw):
+    """48^3 (N_r = 110592): the band chunk is 2^27 / N_r = 1213, so 1300 bands take two chunks."""
+    n = (48, 48, 48)
+    mp = gs.sphere(n, r2=40.0)
+    rng = np.random.default_rng(48)
+    nb = 1300
+    c = (rng.standard_normal((nb, len(mp))) + 1j * rng.standard_normal((nb, len(mp)))).astype(np.complex64)
+    psi = gw.orbitals_to_grid(c64(c), n, mp)
+    torch.cuda.synchronize()
+    pts = np.array([0, 4801, 55296, 110591])
+    rows = np.array([0, 1, 1212, 1213, 1299])
+    got = psi[torch.from_numpy(rows).to(psi.device)][:, torch.from_numpy(pts).to(psi.device)].cpu().numpy()
+    ref = orc.orbitals_on_grid(c[rows].astype(np.complex128), mp, n, points=pts)
+    e = orc.rel_f(got, ref)
+    print(f"48^3 nb={nb} npw={len(mp)}: sampled rel_F {e:.2e}")
+    assert e < 1e-6
+
+
+def test_single_coefficient_edges(gw):
+    n = (6, 6, 6)
+    psi = gw.orbitals_to_grid(c64([[2.0 + 0j]]), n, np.array([[0, 0, 0]])).cpu().numpy()
+    assert np.max(np.abs(psi - 2.0 / np.sqrt(216))) < 1e-7
+    m = np.array([[2, -1, 1]])
+    psi = gw.orbitals_to_grid(c64([[1.0 + 0j], [0.0 + 1j]]), n, m).cpu().numpy()
+    ref = orc.orbitals_on_grid(np.array([[1.0], [1j]]), m, n)
+    assert np.max(np.abs(psi - ref)) < 1e-7
+
+
+def test_feeds_the_polarizability_build(gw):
+    """Coefficients -> grid on the device -> P~, against the same build from host grid orbitals."""
+    s = gs.make_system(12, 8, 64, r2_psi=10.0, seed=2)
+    psi = gw.orbitals_to_grid(c64(s.coeff), s.n, s.pw_miller)
+    pv, pc = psi[:8].contiguous(), psi[8:].contiguous()
+    p_dev = gw.polarizability(pv, pc, s.e_v, s.e_c, s.n, s.a_bohr, s.q, s.miller).cpu().numpy()
+    ref = orc.to_sphere(orc.polarizability_r(s.psi_v, s.psi_c, s.e_v, s.e_c), s.n, s.miller)
+    e = orc.rel_f(p_dev, ref)
+    print(f"P~ from device orbitals: rel_F {e:.2e}")
+    assert e < 1e-5
