@@ -203,6 +203,42 @@ int gw_eps_inverse_newton(gw_ctx *ctx, const gw_c32 *p_gg, int ng, gw_grid grid,
                           void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Plasmon-pole model (the paper's section on the dynamic inverse dielectric
+ * matrix, vdLH-type poles on the polarization part of W):
+ *   S = sqrt(V) (eps^-1 - I) sqrt(V),  S = A diag(sigma) A^H   (Eq.(eigdecomp)),
+ *   omega_a^2 = (A^H M A)_aa / |sigma_a|,                        (Eq.(ppfreq))
+ *   M(g,g') = V(q+g) V(q+g') [(q+g).(q+g')] rho_{g-g'},
+ *   rho(r) = occupation * sum_v |psi_v(r)|^2,  rho_g = sum_r rho(r) exp(-i G.r)
+ * (grid-normalised orbitals, so rho_0 is the electron count; differences g-g'
+ * are taken modulo the grid).  The printed Eq.(ppfreq) divides by sigma_a; since
+ * S is negative semidefinite and M positive semidefinite, |sigma_a| is used,
+ * which is what the sum rule gives through the retarded pole form.
+ * The n_modes most negative sigma (n_modes <= min(24, ng)) come from a block
+ * subspace iteration on -S (block of 32, Rayleigh-Ritz every iteration, FP64)
+ * stopped when max_a ||S a_a - sigma_a a_a|| <= tol |sigma_0|.
+ *   eps_inv [ng][ng] complex128 (device), q host [3] crystal units, g_miller
+ *   host [ng][3], psi_v [nv][N_r] complex64 (device);
+ *   sigma, omega [n_modes] float64 (device), ascending sigma (most negative
+ *   first); modes [ng][n_modes] complex128 (device), column a = A_a (unit norm,
+ *   arbitrary phase); iterations and residual (optional) on the host.
+ * Synchronises `stream` once per iteration.  GW_E_UNSUPPORTED if tol is not
+ * reached in max_iter iterations (the outputs then hold the last Ritz pairs).
+ * ------------------------------------------------------------------------- */
+int gw_plasmon_pole(gw_ctx *ctx, const gw_c64 *eps_inv, int ng, gw_grid grid, const double *q, const int *g_miller,
+                    const gw_c32 *psi_v, int nv, double occupation, int n_modes, double tol, int max_iter,
+                    double *sigma, double *omega, gw_c64 *modes, int *iterations, double *residual, void *stream);
+
+/* Pole form Eq.(ppform) turned back into the dynamic inverse dielectric matrix:
+ *   out[f] = I + V^-1/2 S(w_f) V^-1/2,  S(w) = sum_a A_a sigma_a omega_a^2 / (omega_a^2 - w^2) A_a^H,
+ * for each host frequency freqs[f] (Hartree); rows and columns with sqrt(V) = 0 take
+ * their values from eps_inv_static.  modes/sigma/omega as returned by
+ * gw_plasmon_pole (device); out [nf][ng][ng] complex128 (device).  A frequency
+ * equal to some omega_a gives infinities (the pole). */
+int gw_pp_eps_inverse(gw_ctx *ctx, const gw_c64 *eps_inv_static, int ng, gw_grid grid, const double *q,
+                      const int *g_miller, const gw_c64 *modes, const double *sigma, const double *omega, int n_modes,
+                      const double *freqs, int nf, gw_c64 *out, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Batched q-points (P^q is defined per q, Eq.(staticpol)): each job j runs the
  * whole build and eps^-1 for its own unoccupied set, energies, q and sphere,
  * sharing the occupied set.  The launch sequence of all jobs (kernels only) is

@@ -22,7 +22,8 @@ EXPORTS = ("gw_opts_default", "gw_version", "gw_status_string", "gw_create", "gw
            "gw_sphere_transform", "gw_polarizability", "gw_epsilon", "gw_eps_inverse", "gw_hpd_inverse",
            "gw_polarizability_batched", "gw_autotune", "gw_tail_init", "gw_tail_target", "gw_tail_features",
            "gw_tail_forward", "gw_tail_train_step", "gw_tail_loss", "gw_tail_correct", "gw_newton_inverse",
-           "gw_eps_inverse_newton", "gw_orbitals_to_grid")
+           "gw_eps_inverse_newton", "gw_orbitals_to_grid",
+           "gw_plasmon_pole", "gw_pp_eps_inverse")
 TAIL_NWEIGHT, TAIL_NBIAS, TAIL_NPARAM = 21120, 289, 21409
 
 
@@ -93,6 +94,9 @@ def load() -> C.CDLL:
         "gw_tail_train_step": (i, [vp, C.POINTER(Mlp), C.POINTER(Adam), vp, vp, i, vp, vp]),
         "gw_tail_correct": (i, [vp, C.POINTER(Mlp), vp, i, vp, vp, C.POINTER(i), vp]),
         "gw_tail_loss": (i, [vp, C.POINTER(Mlp), vp, vp, i, vp, vp]),
+        "gw_plasmon_pole": (i, [vp, vp, i, Grid, vp, vp, vp, i, d, i, d, i, vp, vp, vp, C.POINTER(i),
+                                C.POINTER(d), vp]),
+        "gw_pp_eps_inverse": (i, [vp, vp, i, Grid, vp, vp, vp, vp, vp, i, vp, i, vp, vp]),
         "gw_orbitals_to_grid": (i, [vp, vp, i, i, Grid, vp, vp, vp]),
         "gw_newton_inverse": (i, [vp, vp, i, d, i, vp, C.POINTER(i), vp, vp]),
         "gw_eps_inverse_newton": (i, [vp, vp, i, Grid, vp, vp, d, d, i, vp, C.POINTER(i), vp, vp]),
@@ -354,6 +358,50 @@ def orbitals_to_grid(coeff, n, pw_miller, out=None, ctx: Optional[Context] = Non
     st = ctx.lib.gw_orbitals_to_grid(ctx.handle, _dev(coeff, torch.complex64, "coeff"), nb, npw, _grid(nt, 1.0), pm,
                                      _dev(out, torch.complex64, "psi"), _stream(coeff))
     ctx.check(st, "gw_orbitals_to_grid")
+    return out
+
+
+def plasmon_pole(eps_inv, n, a_bohr, q, miller, psi_v, occupation=1.0, n_modes=8, tol=1e-10, max_iter=1000,
+                 ctx: Optional[Context] = None):
+    """The n_modes most negative eigenpairs of S = sqrt(V)(eps^-1 - I)sqrt(V) and their sum-rule
+    frequencies.  Returns (sigma [n_modes] f64, omega [n_modes] f64, modes [ng][n_modes] c128 on the
+    device, iterations, final relative residual)."""
+    import torch
+    m, pm = _host_i32(miller, "g_miller")
+    ng = m.shape[0]
+    qa, pq = _host_f64(q, "q")
+    dev = eps_inv.device
+    sigma = torch.empty(n_modes, dtype=torch.float64, device=dev)
+    omega = torch.empty(n_modes, dtype=torch.float64, device=dev)
+    modes = torch.empty((ng, n_modes), dtype=torch.complex128, device=dev)
+    ctx = ctx or context(dev.index)
+    its, res = C.c_int(0), C.c_double(0.0)
+    st = ctx.lib.gw_plasmon_pole(ctx.handle, _dev(eps_inv, torch.complex128, "eps_inv"), ng, _grid(n, a_bohr), pq, pm,
+                                 _dev(psi_v, torch.complex64, "psi_v"), psi_v.shape[0], float(occupation), int(n_modes),
+                                 float(tol), int(max_iter), _dev(sigma, torch.float64, "sigma"),
+                                 _dev(omega, torch.float64, "omega"), _dev(modes, torch.complex128, "modes"),
+                                 C.byref(its), C.byref(res), _stream(eps_inv))
+    ctx.check(st, "gw_plasmon_pole")
+    return sigma, omega, modes, its.value, res.value
+
+
+def pp_eps_inverse(eps_inv_static, n, a_bohr, q, miller, modes, sigma, omega, freqs, out=None,
+                   ctx: Optional[Context] = None):
+    """eps^-1(w) of the pole form for each frequency in freqs (Hartree): [nf][ng][ng] complex128."""
+    import torch
+    m, pm = _host_i32(miller, "g_miller")
+    ng = m.shape[0]
+    qa, pq = _host_f64(q, "q")
+    fr, pf = _host_f64(np.atleast_1d(np.asarray(freqs, np.float64)), "freqs")
+    nm = modes.shape[1]
+    if out is None:
+        out = torch.empty((len(fr), ng, ng), dtype=torch.complex128, device=modes.device)
+    ctx = ctx or context(modes.device.index)
+    st = ctx.lib.gw_pp_eps_inverse(ctx.handle, _dev(eps_inv_static, torch.complex128, "eps_inv_static"), ng,
+                                   _grid(n, a_bohr), pq, pm, _dev(modes, torch.complex128, "modes"),
+                                   _dev(sigma, torch.float64, "sigma"), _dev(omega, torch.float64, "omega"), nm, pf,
+                                   len(fr), _dev(out, torch.complex128, "out"), _stream(modes))
+    ctx.check(st, "gw_pp_eps_inverse")
     return out
 
 

@@ -112,6 +112,12 @@ static hipError_t zgemm(int M, int N, int K, const double2 *A, long long lda, in
   return hipGetLastError();
 }
 
+hipError_t launch_zgemm(int M, int N, int K, const double2 *A, long long lda, int transA, const double2 *B,
+                        long long ldb, int transB, double2 *C, long long ldc, double alpha, double beta,
+                        hipStream_t s) {
+  return zgemm(M, N, K, A, lda, transA, B, ldb, transB, C, ldc, alpha, beta, 0, 0, s);
+}
+
 // ---- diagonal block: L_kk = chol(A_kk) and Linv_kk = L_kk^-1 (one workgroup) ------------------
 constexpr int NB = 32;
 

@@ -65,31 +65,6 @@ void store_tune_file(const std::string &key, int tile) {
   f << key << ' ' << tile << '\n';
 }
 
-#define B_CHECK(ctx, cond, msg)      \
-  do {                               \
-    if (!(cond)) {                   \
-      api_set_err((ctx), (msg));     \
-      return GW_E_INVAL;             \
-    }                                \
-  } while (0)
-
-#define B_HIP(ctx, call)                                                                  \
-  do {                                                                                    \
-    hipError_t e_ = (call);                                                               \
-    if (e_ != hipSuccess) {                                                               \
-      char b_[320];                                                                       \
-      snprintf(b_, sizeof(b_), "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
-      api_set_err((ctx), b_);                                                             \
-      return GW_E_HIP;                                                                    \
-    }                                                                                     \
-  } while (0)
-
-#define B_STATUS(expr)             \
-  do {                             \
-    int st_ = (expr);              \
-    if (st_ != GW_OK) return st_;  \
-  } while (0)
-
 // Workspace slots private to the batched path (so a graph's baked-in addresses stay valid).
 enum {
   BS_P0 = 64, BS_P1, BS_A1, BS_A2, BS_PH, BS_PHT, BS_Q, BS_EPS, BS_L, BS_X, BS_SMALL, BS_PIVOT,
@@ -146,18 +121,18 @@ int autotune_impl(gw_ctx *ctx, const float2 *psi_v, int nv, const float2 *psi_c,
   const int nt = std::min(nv, 8);
   const int ldsc = scale_ld(nc);
   void *eb, *sb, *bx;
-  B_STATUS(api_ws_get(ctx, WS_ENERGY, (size_t)(nv + nc) * sizeof(double), &eb, s));
-  B_STATUS(api_ws_get(ctx, WS_SCALE, (size_t)nv * ldsc * sizeof(float), &sb, s));
-  B_STATUS(api_ws_get(ctx, WS_BSCALE, (size_t)(2 * nv + nc) * sizeof(int), &bx, s));
+  GWX_STATUS(api_ws_get(ctx, WS_ENERGY, (size_t)(nv + nc) * sizeof(double), &eb, s));
+  GWX_STATUS(api_ws_get(ctx, WS_SCALE, (size_t)nv * ldsc * sizeof(float), &sb, s));
+  GWX_STATUS(api_ws_get(ctx, WS_BSCALE, (size_t)(2 * nv + nc) * sizeof(int), &bx, s));
   double *de = (double *)eb;
-  B_HIP(ctx, hipMemcpyAsync(de, e_v, nt * sizeof(double), hipMemcpyHostToDevice, s));
-  B_HIP(ctx, hipMemcpyAsync(de + nt, e_c, nc * sizeof(double), hipMemcpyHostToDevice, s));
-  B_HIP(ctx, launch_scale_table(de, nt, de + nt, nc, 1.0, (float *)sb, ldsc, s));
-  B_HIP(ctx, launch_band_exponents(psi_v, nt, psi_c, nc, nr, (const float *)sb, ldsc, (int *)bx, s));
+  GWX_HIP(ctx, hipMemcpyAsync(de, e_v, nt * sizeof(double), hipMemcpyHostToDevice, s));
+  GWX_HIP(ctx, hipMemcpyAsync(de + nt, e_c, nc * sizeof(double), hipMemcpyHostToDevice, s));
+  GWX_HIP(ctx, launch_scale_table(de, nt, de + nt, nc, 1.0, (float *)sb, ldsc, s));
+  GWX_HIP(ctx, launch_band_exponents(psi_v, nt, psi_c, nc, nr, (const float *)sb, ldsc, (int *)bx, s));
   float2 *pb = p_scratch;
   hipEvent_t e0, e1;
-  B_HIP(ctx, hipEventCreate(&e0));
-  B_HIP(ctx, hipEventCreate(&e1));
+  GWX_HIP(ctx, hipEventCreate(&e0));
+  GWX_HIP(ctx, hipEventCreate(&e1));
   int bt = -1;
   float bms = 0.f;
   for (int t = 0; t < herk_tile_count(); ++t) {
@@ -165,12 +140,12 @@ int autotune_impl(gw_ctx *ctx, const float2 *psi_v, int nv, const float2 *psi_c,
     if (!herk_tile_supports(t, precision)) continue;
     float ms = 0.f;
     for (int rep = 0; rep < 2; ++rep) {       // first launch warms caches and code
-      B_HIP(ctx, hipEventRecord(e0, s));
-      B_HIP(ctx, launch_herk(precision, t, psi_v, psi_c, (const float *)sb, ldsc, (const int *)bx, (float2 *)pb, nr,
+      GWX_HIP(ctx, hipEventRecord(e0, s));
+      GWX_HIP(ctx, launch_herk(precision, t, psi_v, psi_c, (const float *)sb, ldsc, (const int *)bx, (float2 *)pb, nr,
                              nt, nc, 0, s));   // writes the whole P scratch
-      B_HIP(ctx, hipEventRecord(e1, s));
-      B_HIP(ctx, hipEventSynchronize(e1));
-      B_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+      GWX_HIP(ctx, hipEventRecord(e1, s));
+      GWX_HIP(ctx, hipEventSynchronize(e1));
+      GWX_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
     }
     if (times_ms) times_ms[t] = ms;
     if (bt < 0 || ms < bms) { bt = t; bms = ms; }
@@ -204,14 +179,14 @@ extern "C" {
 
 int gw_autotune(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *psi_c, int nc, int nr, const double *e_v,
                 const double *e_c, int precision, gw_c32 *p_scratch, int *best_tile, double *times_ms, void *stream) {
-  B_STATUS(api_begin(ctx));
-  B_CHECK(ctx, psi_v && psi_c && best_tile && p_scratch, "psi_v, psi_c, p_scratch and best_tile must not be NULL");
-  B_CHECK(ctx, nv > 0 && nc > 0 && nr > 0 && nr <= (1 << 24), "nv, nc, nr out of range");
+  GWX_STATUS(api_begin(ctx));
+  GWX_CHECK(ctx, psi_v && psi_c && best_tile && p_scratch, "psi_v, psi_c, p_scratch and best_tile must not be NULL");
+  GWX_CHECK(ctx, nv > 0 && nc > 0 && nr > 0 && nr <= (1 << 24), "nv, nc, nr out of range");
   gw_opts o;
   gw_opts_default(&o);
   o.precision = precision;
-  B_STATUS(api_check_opts(ctx, &o));
-  B_STATUS(api_check_energies(ctx, e_v, nv, e_c, nc));
+  GWX_STATUS(api_check_opts(ctx, &o));
+  GWX_STATUS(api_check_energies(ctx, e_v, nv, e_c, nc));
   if (ctx->device < 0) { *best_tile = -1; return GW_OK; }
   return autotune_impl(ctx, (const float2 *)psi_v, nv, (const float2 *)psi_c, nc, nr, e_v, e_c, precision,
                        (float2 *)p_scratch, best_tile, times_ms, reinterpret_cast<hipStream_t>(stream));
@@ -219,30 +194,30 @@ int gw_autotune(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *psi_c, i
 
 int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const double *e_v, gw_grid grid, int nq,
                               const gw_qjob *jobs, const gw_opts *opts, double head, void *stream) {
-  B_STATUS(api_begin(ctx));
+  GWX_STATUS(api_begin(ctx));
   gw_opts o;
   gw_opts_default(&o);
   if (opts) o = *opts;
-  B_CHECK(ctx, nq > 0 && nq <= kMaxJobs, "nq must be in [1, 64]");
-  B_CHECK(ctx, jobs != nullptr && psi_occ != nullptr && e_v != nullptr, "jobs, psi_occ and e_v must not be NULL");
-  B_CHECK(ctx, nv > 0, "nv must be positive");
-  B_CHECK(ctx, o.accumulate == 0, "accumulate is not available for batched builds");
-  B_STATUS(api_check_opts(ctx, &o));
-  B_STATUS(api_check_grid(ctx, grid));
+  GWX_CHECK(ctx, nq > 0 && nq <= kMaxJobs, "nq must be in [1, 64]");
+  GWX_CHECK(ctx, jobs != nullptr && psi_occ != nullptr && e_v != nullptr, "jobs, psi_occ and e_v must not be NULL");
+  GWX_CHECK(ctx, nv > 0, "nv must be positive");
+  GWX_CHECK(ctx, o.accumulate == 0, "accumulate is not available for batched builds");
+  GWX_STATUS(api_check_opts(ctx, &o));
+  GWX_STATUS(api_check_grid(ctx, grid));
   const long long nrl = (long long)grid.n1 * grid.n2 * grid.n3;
-  B_CHECK(ctx, nrl <= (1 << 24), "grid too large");
+  GWX_CHECK(ctx, nrl <= (1 << 24), "grid too large");
   const int nr = (int)nrl;
   if (std::isnan(head)) head = 1.0;
-  B_CHECK(ctx, std::isfinite(head) && head > 0.0, "head must be positive");
+  GWX_CHECK(ctx, std::isfinite(head) && head > 0.0, "head must be positive");
   for (int j = 0; j < nq; ++j) {
     const gw_qjob &jb = jobs[j];
-    B_CHECK(ctx, jb.psi_unocc && jb.p_gg && jb.e_c && jb.g_miller, "job pointers must not be NULL (eps_inv may be)");
-    B_CHECK(ctx, jb.nc > 0 && (long long)nv * jb.nc <= (1LL << 31), "job nc out of range");
-    B_CHECK(ctx, std::isfinite(jb.q[0]) && std::isfinite(jb.q[1]) && std::isfinite(jb.q[2]), "q must be finite");
-    B_STATUS(api_check_energies(ctx, e_v, nv, jb.e_c, jb.nc));
-    B_STATUS(api_check_sphere(ctx, grid, jb.g_miller, jb.ng));
+    GWX_CHECK(ctx, jb.psi_unocc && jb.p_gg && jb.e_c && jb.g_miller, "job pointers must not be NULL (eps_inv may be)");
+    GWX_CHECK(ctx, jb.nc > 0 && (long long)nv * jb.nc <= (1LL << 31), "job nc out of range");
+    GWX_CHECK(ctx, std::isfinite(jb.q[0]) && std::isfinite(jb.q[1]) && std::isfinite(jb.q[2]), "q must be finite");
+    GWX_STATUS(api_check_energies(ctx, e_v, nv, jb.e_c, jb.nc));
+    GWX_STATUS(api_check_sphere(ctx, grid, jb.g_miller, jb.ng));
   }
-  B_STATUS(api_grid_supported(ctx, grid));
+  GWX_STATUS(api_grid_supported(ctx, grid));
   if (ctx->device < 0) return GW_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
@@ -260,29 +235,29 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
   void *pbuf[2] = {nullptr, nullptr};
   std::vector<void *> ptrs;
   for (int b = 0; b < np; ++b) {
-    B_STATUS(api_ws_get(ctx, BS_P0 + b, (size_t)nr * nr * sizeof(float2), &pbuf[b], s));
+    GWX_STATUS(api_ws_get(ctx, BS_P0 + b, (size_t)nr * nr * sizeof(float2), &pbuf[b], s));
     ptrs.push_back(pbuf[b]);
   }
   for (int j = 0; j < nq; ++j) {
     int t = o.tile;
     if (t < 0) t = tuned_tile(ctx, nr, nv, jobs[j].nc, o.precision);
     if (t < 0) {
-      B_STATUS(autotune_impl(ctx, (const float2 *)psi_occ, nv, (const float2 *)jobs[j].psi_unocc, jobs[j].nc, nr, e_v,
+      GWX_STATUS(autotune_impl(ctx, (const float2 *)psi_occ, nv, (const float2 *)jobs[j].psi_unocc, jobs[j].nc, nr, e_v,
                              jobs[j].e_c, o.precision, (float2 *)pbuf[0], &t, nullptr, s));
     }
     tiles[j] = t;
   }
   void *wa1, *wa2, *wph, *wpht, *wq, *weps, *wl, *wx, *wsmall, *wpiv;
-  B_STATUS(api_ws_get(ctx, BS_A1, a1 * sizeof(float2), &wa1, s));
-  B_STATUS(api_ws_get(ctx, BS_A2, a2 * sizeof(float2), &wa2, s));
-  B_STATUS(api_ws_get(ctx, BS_PH, ngmax * nr * sizeof(float2), &wph, s));
-  B_STATUS(api_ws_get(ctx, BS_PHT, ngmax * nr * sizeof(float2), &wpht, s));
-  B_STATUS(api_ws_get(ctx, BS_Q, ngmax * ngmax * sizeof(float2), &wq, s));
-  B_STATUS(api_ws_get(ctx, BS_EPS, ngmax * ngmax * sizeof(double2), &weps, s));
-  B_STATUS(api_ws_get(ctx, BS_L, ngmax * ngmax * sizeof(double2), &wl, s));
-  B_STATUS(api_ws_get(ctx, BS_X, ngmax * ngmax * sizeof(double2), &wx, s));
-  B_STATUS(api_ws_get(ctx, BS_SMALL, chol_small_bytes((int)ngmax), &wsmall, s));
-  B_STATUS(api_ws_get(ctx, BS_PIVOT, (size_t)nq * 64, &wpiv, s));
+  GWX_STATUS(api_ws_get(ctx, BS_A1, a1 * sizeof(float2), &wa1, s));
+  GWX_STATUS(api_ws_get(ctx, BS_A2, a2 * sizeof(float2), &wa2, s));
+  GWX_STATUS(api_ws_get(ctx, BS_PH, ngmax * nr * sizeof(float2), &wph, s));
+  GWX_STATUS(api_ws_get(ctx, BS_PHT, ngmax * nr * sizeof(float2), &wpht, s));
+  GWX_STATUS(api_ws_get(ctx, BS_Q, ngmax * ngmax * sizeof(float2), &wq, s));
+  GWX_STATUS(api_ws_get(ctx, BS_EPS, ngmax * ngmax * sizeof(double2), &weps, s));
+  GWX_STATUS(api_ws_get(ctx, BS_L, ngmax * ngmax * sizeof(double2), &wl, s));
+  GWX_STATUS(api_ws_get(ctx, BS_X, ngmax * ngmax * sizeof(double2), &wx, s));
+  GWX_STATUS(api_ws_get(ctx, BS_SMALL, chol_small_bytes((int)ngmax), &wsmall, s));
+  GWX_STATUS(api_ws_get(ctx, BS_PIVOT, (size_t)nq * 64, &wpiv, s));
   for (void *p : {wa1, wa2, wph, wpht, wq, weps, wl, wx, wsmall, wpiv}) ptrs.push_back(p);
   struct JobDev { double *energy; float *scale; int *bexp; int *maps; int *miller; double *sqrtv; };
   std::vector<JobDev> jd(nq);
@@ -295,7 +270,7 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
                                      (pl.mapA.size() + pl.mapB.size() + pl.mapC.size()) * sizeof(int),
                                      (size_t)ng * 3 * sizeof(int), (size_t)ng * sizeof(double)};
     for (int k = 0; k < kJobSlots; ++k) {
-      B_STATUS(api_ws_get(ctx, BS_JOB_BASE + kJobSlots * j + k, bytes[k], &p[k], s));
+      GWX_STATUS(api_ws_get(ctx, BS_JOB_BASE + kJobSlots * j + k, bytes[k], &p[k], s));
       ptrs.push_back(p[k]);
     }
     jd[j] = {(double *)p[0], (float *)p[1], (int *)p[2], (int *)p[3], (int *)p[4], (double *)p[5]};
@@ -305,15 +280,15 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
   for (int j = 0; j < nq; ++j) {
     const gw_qjob &jb = jobs[j];
     const SpherePlan &pl = plans[j];
-    B_HIP(ctx, hipMemcpyAsync(jd[j].energy, e_v, nv * sizeof(double), hipMemcpyHostToDevice, s));
-    B_HIP(ctx, hipMemcpyAsync(jd[j].energy + nv, jb.e_c, jb.nc * sizeof(double), hipMemcpyHostToDevice, s));
+    GWX_HIP(ctx, hipMemcpyAsync(jd[j].energy, e_v, nv * sizeof(double), hipMemcpyHostToDevice, s));
+    GWX_HIP(ctx, hipMemcpyAsync(jd[j].energy + nv, jb.e_c, jb.nc * sizeof(double), hipMemcpyHostToDevice, s));
     int *m = jd[j].maps;
-    B_HIP(ctx, hipMemcpyAsync(m, pl.mapA.data(), pl.mapA.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    GWX_HIP(ctx, hipMemcpyAsync(m, pl.mapA.data(), pl.mapA.size() * sizeof(int), hipMemcpyHostToDevice, s));
     m += pl.mapA.size();
-    B_HIP(ctx, hipMemcpyAsync(m, pl.mapB.data(), pl.mapB.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    GWX_HIP(ctx, hipMemcpyAsync(m, pl.mapB.data(), pl.mapB.size() * sizeof(int), hipMemcpyHostToDevice, s));
     m += pl.mapB.size();
-    B_HIP(ctx, hipMemcpyAsync(m, pl.mapC.data(), pl.mapC.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    B_HIP(ctx, hipMemcpyAsync(jd[j].miller, jb.g_miller, (size_t)jb.ng * 3 * sizeof(int), hipMemcpyHostToDevice, s));
+    GWX_HIP(ctx, hipMemcpyAsync(m, pl.mapC.data(), pl.mapC.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    GWX_HIP(ctx, hipMemcpyAsync(jd[j].miller, jb.g_miller, (size_t)jb.ng * 3 * sizeof(int), hipMemcpyHostToDevice, s));
   }
 
   // ---- graph key: everything baked into the captured launches ---------------------------------
@@ -339,18 +314,18 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
   Cached *c = cache_of(ctx);
   if (c->key != key || c->ptrs != ptrs || !c->exec) {
     drop_graph(c);
-    if (!c->sa) B_HIP(ctx, hipStreamCreateWithFlags(&c->sa, hipStreamNonBlocking));
-    if (!c->sb) B_HIP(ctx, hipStreamCreateWithFlags(&c->sb, hipStreamNonBlocking));
+    if (!c->sa) GWX_HIP(ctx, hipStreamCreateWithFlags(&c->sa, hipStreamNonBlocking));
+    if (!c->sb) GWX_HIP(ctx, hipStreamCreateWithFlags(&c->sb, hipStreamNonBlocking));
     const size_t nev = 2 + 2 * (size_t)nq;
     while (c->events.size() < nev) {
       hipEvent_t e;
-      B_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      GWX_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
       c->events.push_back(e);
     }
     hipEvent_t ev_fork = c->events[0], ev_join = c->events[1];
     hipEvent_t *ev_herk = &c->events[2], *ev_post = &c->events[2 + nq];
     // the capture hangs off sa; sa waits for the caller's stream so uploads precede the replay
-    B_HIP(ctx, hipStreamBeginCapture(c->sa, hipStreamCaptureModeThreadLocal));
+    GWX_HIP(ctx, hipStreamBeginCapture(c->sa, hipStreamCaptureModeThreadLocal));
     hipError_t ce = hipSuccess;
     auto ck = [&](hipError_t e) { if (ce == hipSuccess && e != hipSuccess) ce = e; };
     ck(hipEventRecord(ev_fork, c->sa));
@@ -394,23 +369,23 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
       return GW_E_HIP;
     }
     c->graph = g;
-    B_HIP(ctx, hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
+    GWX_HIP(ctx, hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
     c->key = key;
     c->ptrs = ptrs;
   }
   if (c->npiv < nq) {
     if (c->pivots_host) (void)hipHostFree(c->pivots_host);
     c->pivots_host = nullptr;
-    B_HIP(ctx, hipHostMalloc((void **)&c->pivots_host, (size_t)nq * sizeof(int), hipHostMallocDefault));
+    GWX_HIP(ctx, hipHostMalloc((void **)&c->pivots_host, (size_t)nq * sizeof(int), hipHostMallocDefault));
     c->npiv = nq;
   }
-  B_HIP(ctx, hipGraphLaunch(c->exec, s));
+  GWX_HIP(ctx, hipGraphLaunch(c->exec, s));
   for (int j = 0; j < nq; ++j) {
     c->pivots_host[j] = 0;
     if (jobs[j].eps_inv)
-      B_HIP(ctx, hipMemcpyAsync(&c->pivots_host[j], (char *)wpiv + 64 * j, sizeof(int), hipMemcpyDeviceToHost, s));
+      GWX_HIP(ctx, hipMemcpyAsync(&c->pivots_host[j], (char *)wpiv + 64 * j, sizeof(int), hipMemcpyDeviceToHost, s));
   }
-  B_HIP(ctx, hipStreamSynchronize(s));
+  GWX_HIP(ctx, hipStreamSynchronize(s));
   for (int j = 0; j < nq; ++j) {
     if (c->pivots_host[j] != 0) {
       char b[160];

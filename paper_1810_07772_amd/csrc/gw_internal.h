@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdio>
 #include <cstdint>
 #include <map>
 #include <string>
@@ -96,6 +97,29 @@ size_t chol_small_bytes(int n);
 hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small, int *pivot_dev, double2 *out,
                        hipStream_t s);
 hipError_t launch_fill_int(int *p, int value, hipStream_t s);
+// C = alpha op(A) op(B) + beta C, complex128, op = identity (0) or conjugate transpose (1); row-major.
+hipError_t launch_zgemm(int M, int N, int K, const double2 *A, long long lda, int transA, const double2 *B,
+                        long long ldb, int transB, double2 *C, long long ldc, double alpha, double beta,
+                        hipStream_t s);
+// Plasmon-pole kernels (pp.hip)
+hipError_t launch_density(const float2 *psi, int nv, int nr, double occ, double2 *rho, hipStream_t s);
+hipError_t launch_density_transform(double2 *rho, double2 *tmp, int n1, int n2, int n3, hipStream_t s);
+hipError_t launch_screening(const double2 *ei, const double *sv, int ng, double2 *out, hipStream_t s);
+hipError_t launch_sum_rule(const int *miller, int ng, const double *q, double a_bohr, const double *sv,
+                           const double2 *rho_g, int n1, int n2, int n3, double2 *m, hipStream_t s);
+hipError_t launch_start_block(double2 *x, int ng, int b, unsigned long long seed, hipStream_t s);
+hipError_t launch_herm_jacobi(const double2 *h, int b, int ldh, double *evals, double2 *z, int ldz, hipStream_t s);
+hipError_t launch_col_normalize(double2 *w, int rows, int ld, int cols, hipStream_t s);
+hipError_t launch_svqb_scale(double2 *u, const double *lam, int b, double rel, hipStream_t s);
+hipError_t launch_ritz_residual(const double2 *x, const double2 *y, int ng, int ld, const double *theta, int nm,
+                                double *out, hipStream_t s);
+hipError_t launch_pp_frequency(const double2 *a, int lda, const double2 *t, int ldt, int ng, const double *theta,
+                               int nm, double *sigma, double *omega, hipStream_t s);
+hipError_t launch_pp_weight(const double2 *modes, int ng, int nm, const double *sigma, const double *omega, double w,
+                            double2 *out, hipStream_t s);
+hipError_t launch_pp_finish(double2 *e, const double2 *ei_static, const double *sv, int ng, hipStream_t s);
+hipError_t launch_sqrtv(const int *miller, int ng, double q0, double q1, double q2, double a_bohr, double *sv,
+                        hipStream_t s);
 // Newton iteration for the inverse: workspace of newton_ws_bytes(n) holds x, t, xn and the scalars.
 size_t newton_ws_bytes(int n);
 hipError_t newton_start(const double2 *a, int n, double2 *x, double2 *t, double *scratch, hipStream_t s);
@@ -153,3 +177,29 @@ int autotune_impl(gw_ctx *ctx, const float2 *psi_v, int nv, const float2 *psi_c,
                   const double *e_c, int precision, float2 *p_scratch, int *best, double *times_ms, hipStream_t s);
 
 }  // namespace gwi
+
+// Error macros of the host files other than gw_api.cpp (they report through api_set_err).
+#define GWX_CHECK(ctx, cond, msg)    \
+  do {                               \
+    if (!(cond)) {                   \
+      gwi::api_set_err((ctx), (msg)); \
+      return GW_E_INVAL;             \
+    }                                \
+  } while (0)
+
+#define GWX_HIP(ctx, call)                                                                                    \
+  do {                                                                                                        \
+    hipError_t e_ = (call);                                                                                   \
+    if (e_ != hipSuccess) {                                                                                   \
+      char b_[320];                                                                                           \
+      snprintf(b_, sizeof(b_), "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__);  \
+      gwi::api_set_err((ctx), b_);                                                                            \
+      return GW_E_HIP;                                                                                        \
+    }                                                                                                         \
+  } while (0)
+
+#define GWX_STATUS(expr)           \
+  do {                             \
+    int st_ = (expr);              \
+    if (st_ != GW_OK) return st_;  \
+  } while (0)

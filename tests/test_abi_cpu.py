@@ -145,6 +145,19 @@ def test_dry_run_other_entry_points(gw):
     assert lib.gw_orbitals_to_grid(h, vp(), 3, len(m), grid, i32(dup)[1], vp(), None) == 1
     m7, pm7 = i32(gs.sphere((7, 7, 7), r2=2.0))
     assert lib.gw_orbitals_to_grid(h, vp(), 3, len(m7), gw._lib.Grid(7, 7, 7, 6.0), pm7, vp(), None) == 5
+    # plasmon-pole model
+    its, res = C.c_int(-1), C.c_double(0.0)
+    pp = lambda **kw: lib.gw_plasmon_pole(h, vp(), len(m), grid, pq, pm, vp(), kw.get("nv", 4), kw.get("occ", 2.0),
+                                          kw.get("nm", 8), kw.get("tol", 1e-10), kw.get("it", 100), vp(), vp(),
+                                          kw.get("modes", vp()), C.byref(its), C.byref(res), None)
+    assert pp() == 0 and its.value == 0
+    assert pp(nm=0) == 1 and pp(nm=25) == 1 and pp(nm=len(m) + 1) == 1
+    assert pp(occ=0.0) == 1 and pp(tol=0.0) == 1 and pp(it=0) == 1 and pp(nv=0) == 1 and pp(modes=vp(0)) == 1
+    fr, pfr = f64([0.0, 0.5])
+    assert lib.gw_pp_eps_inverse(h, vp(), len(m), grid, pq, pm, vp(), vp(), vp(), 4, pfr, 2, vp(), None) == 0
+    assert lib.gw_pp_eps_inverse(h, vp(), len(m), grid, pq, pm, vp(), vp(), vp(), 4, pfr, 0, vp(), None) == 1
+    frn, pfrn = f64([np.nan])
+    assert lib.gw_pp_eps_inverse(h, vp(), len(m), grid, pq, pm, vp(), vp(), vp(), 4, pfrn, 1, vp(), None) == 1
     # Newton iteration arguments
     its = C.c_int(-1)
     assert lib.gw_newton_inverse(h, vp(), 10, 1e-11, 50, vp(), C.byref(its), None, None) == 0 and its.value == 0
