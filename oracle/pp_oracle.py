@@ -2,8 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the benchmark's CPU
 baseline, never by the library.  Each function is the plain definition of the paper's
-section on the dynamic inverse dielectric matrix (vdLH-type plasmon poles), with numpy's
-dense Hermitian eigensolver and matrix product as the only library steps.
+section on the dynamic inverse dielectric matrix (vdLH-type plasmon poles), with LAPACK's
+dense Hermitian eigensolver (through scipy), numpy's FFT and matrix product as the only
+library steps.
 
 Readings used here:
 
@@ -50,6 +51,13 @@ def density_g(rho_r, n: Sequence[int], miller) -> np.ndarray:
     return out
 
 
+def density_g_grid(rho_r, n: Sequence[int]) -> np.ndarray:
+    """rho_g for every grid frequency (index m mod n), by numpy's forward FFT: the same sum as
+    density_g, evaluated for all m at once."""
+    n = tuple(int(x) for x in n)
+    return np.fft.fftn(np.asarray(rho_r, np.float64).reshape(n)).ravel()
+
+
 def screening_part(eps_inv, sqrtv) -> np.ndarray:
     """S = sqrt(V) (eps^-1 - I) sqrt(V): the polarization part of the static W (W - V)."""
     sv = np.asarray(sqrtv, np.float64)
@@ -63,9 +71,10 @@ def sum_rule_matrix(n: Sequence[int], a_bohr: float, q, miller, sqrtv, rho_r) ->
     m = np.asarray(miller, np.int64)
     qm = (m + np.asarray(q, np.float64)[None, :]) * (2.0 * np.pi / a_bohr)
     v = np.asarray(sqrtv, np.float64) ** 2
-    diff = (m[:, None, :] - m[None, :, :]).reshape(-1, 3)
-    uniq, inv = np.unique(diff, axis=0, return_inverse=True)
-    rho = density_g(rho_r, n, uniq)[inv.ravel()].reshape(len(m), len(m))
+    n = tuple(int(x) for x in n)
+    rg = density_g_grid(rho_r, n)
+    d = [(m[:, None, k] - m[None, :, k]) % n[k] for k in range(3)]
+    rho = rg[(d[0] * n[1] + d[1]) * n[2] + d[2]]
     return v[:, None] * v[None, :] * (qm @ qm.T) * rho
 
 
@@ -73,11 +82,12 @@ def plasmon_pole(eps_inv, n: Sequence[int], a_bohr: float, q, miller, sqrtv, psi
                  n_modes: int = 8):
     """Eq.(eigdecomp) and Eq.(ppfreq): the n_modes most negative eigenpairs (sigma_a, A[:, a]) of S
     and their frequencies omega_a.  Returns (sigma [n_modes], omega [n_modes], A [ng][n_modes])."""
+    import scipy.linalg
     s = screening_part(eps_inv, sqrtv)
-    w, a = np.linalg.eigh(0.5 * (s + np.conj(s).T))     # ascending: most negative first
-    w, a = w[:n_modes], a[:, :n_modes]
+    # ascending eigenvalues, so the first n_modes are the most negative
+    w, a = scipy.linalg.eigh(0.5 * (s + np.conj(s).T), subset_by_index=[0, n_modes - 1])
     mm = sum_rule_matrix(n, a_bohr, q, miller, sqrtv, density_r(psi_v, occupation))
-    num = np.real(np.einsum("ga,gh,ha->a", np.conj(a), mm, a))
+    num = np.real(np.sum(np.conj(a) * (mm @ a), axis=0))
     return w, np.sqrt(num / np.abs(w)), a
 
 

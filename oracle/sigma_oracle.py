@@ -42,7 +42,8 @@ def sigma_sex(ft, s_gg) -> np.ndarray:
     """Static screened exchange, T form: Sigma_sex(n,n') = sum_v sum_g f~_g^{nv} T_g^{n'v} with
     T_g^{n'v} = -sum_g' S(g,g') conj(f~_g'^{n'v})."""
     ft = np.asarray(ft, np.complex128)
-    t = -np.einsum("gh,bvh->bvg", np.asarray(s_gg, np.complex128), np.conj(ft))
+    nn, nv, ng = ft.shape
+    t = -(np.conj(ft).reshape(nn * nv, ng) @ np.asarray(s_gg, np.complex128).T).reshape(nn, nv, ng)
     return np.einsum("avg,bvg->ab", ft, t)
 
 

@@ -41,6 +41,15 @@ def test_density_electron_count_and_reality():
     assert np.max(np.abs(gm - np.conj(g))) < 1e-13
 
 
+def test_density_on_the_grid_equals_the_direct_sum():
+    s = gs.make_system(6, 5, 7, r2_psi=4.0, seed=2)
+    rho = pp.density_r(s.psi_v, 1.0)
+    m = gs.sphere(s.n, r2=8.0)
+    full = pp.density_g_grid(rho, s.n)
+    idx = ((m[:, 0] % 6) * 6 + m[:, 1] % 6) * 6 + m[:, 2] % 6
+    assert np.max(np.abs(full[idx] - pp.density_g(rho, s.n, m))) < 1e-13
+
+
 def test_sum_rule_matrix_orientation():
     """M(g1, g2) carries rho_{g1-g2}: with the phase-i density above that is -i occ/2, not +i occ/2."""
     n = (4, 4, 4)
