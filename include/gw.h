@@ -239,6 +239,31 @@ int gw_pp_eps_inverse(gw_ctx *ctx, const gw_c64 *eps_inv_static, int ng, gw_grid
                       const double *freqs, int nf, gw_c64 *out, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Static self-energy matrix elements in g-space (the paper's self-energy
+ * section, one q, N_k = 1), for a band list n (psi_n [nn][N_r]) and the
+ * occupied set v (psi_v [nv][N_r]), both complex64 on the device:
+ *   f~_g^{nv} = sum_r exp(-i G_g.r) conj(u_n(r)) u_v(r)         (FP32 transform)
+ *   sigma_x[n][n']   = -sum_g V(q+g) sum_v f~_g^{nv} conj(f~_g^{n'v})
+ *   sigma_sex[n][n'] = -sum_v sum_{g,g'} f~_g^{nv} S(g,g') conj(f~_g'^{n'v}),
+ *                      S = sqrt(V) (eps^-1 - I) sqrt(V)           (T form)
+ * with FP64 contractions (the T = S conj(f~) product on the FP64 MFMA GEMM).
+ *   eps_inv [ng][ng] complex128 (device; may be NULL when sigma_sex is NULL);
+ *   sigma_x, sigma_sex [nn][nn] complex128 (device), either may be NULL.
+ *   nn <= 256; grid sides as for gw_sphere_transform.
+ * ------------------------------------------------------------------------- */
+int gw_sigma_static(gw_ctx *ctx, const gw_c32 *psi_n, int nn, const gw_c32 *psi_v, int nv, gw_grid grid,
+                    const double *q, const int *g_miller, int ng, const gw_c64 *eps_inv, gw_c64 *sigma_x,
+                    gw_c64 *sigma_sex, void *stream);
+
+/* Screened exchange in the eigen form: zeta_a^{nv} = sum_g f~_g^{nv} A(g,a),
+ *   sigma_sex[n][n'] = -sum_a sigma_a sum_v zeta_a^{nv} conj(zeta_a^{n'v}),
+ * with modes [ng][n_modes] complex128 and sigma [n_modes] float64 as returned by
+ * gw_plasmon_pole (device). */
+int gw_sigma_sex_modes(gw_ctx *ctx, const gw_c32 *psi_n, int nn, const gw_c32 *psi_v, int nv, gw_grid grid,
+                       const int *g_miller, int ng, const gw_c64 *modes, const double *sigma, int n_modes,
+                       gw_c64 *sigma_sex, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Batched q-points (P^q is defined per q, Eq.(staticpol)): each job j runs the
  * whole build and eps^-1 for its own unoccupied set, energies, q and sphere,
  * sharing the occupied set.  The launch sequence of all jobs (kernels only) is

@@ -23,7 +23,7 @@ EXPORTS = ("gw_opts_default", "gw_version", "gw_status_string", "gw_create", "gw
            "gw_polarizability_batched", "gw_autotune", "gw_tail_init", "gw_tail_target", "gw_tail_features",
            "gw_tail_forward", "gw_tail_train_step", "gw_tail_loss", "gw_tail_correct", "gw_newton_inverse",
            "gw_eps_inverse_newton", "gw_orbitals_to_grid",
-           "gw_plasmon_pole", "gw_pp_eps_inverse")
+           "gw_plasmon_pole", "gw_pp_eps_inverse", "gw_sigma_static", "gw_sigma_sex_modes")
 TAIL_NWEIGHT, TAIL_NBIAS, TAIL_NPARAM = 21120, 289, 21409
 
 
@@ -97,6 +97,8 @@ def load() -> C.CDLL:
         "gw_plasmon_pole": (i, [vp, vp, i, Grid, vp, vp, vp, i, d, i, d, i, vp, vp, vp, C.POINTER(i),
                                 C.POINTER(d), vp]),
         "gw_pp_eps_inverse": (i, [vp, vp, i, Grid, vp, vp, vp, vp, vp, i, vp, i, vp, vp]),
+        "gw_sigma_static": (i, [vp, vp, i, vp, i, Grid, vp, vp, i, vp, vp, vp, vp]),
+        "gw_sigma_sex_modes": (i, [vp, vp, i, vp, i, Grid, vp, i, vp, vp, i, vp, vp]),
         "gw_orbitals_to_grid": (i, [vp, vp, i, i, Grid, vp, vp, vp]),
         "gw_newton_inverse": (i, [vp, vp, i, d, i, vp, C.POINTER(i), vp, vp]),
         "gw_eps_inverse_newton": (i, [vp, vp, i, Grid, vp, vp, d, d, i, vp, C.POINTER(i), vp, vp]),
@@ -402,6 +404,44 @@ def pp_eps_inverse(eps_inv_static, n, a_bohr, q, miller, modes, sigma, omega, fr
                                    _dev(sigma, torch.float64, "sigma"), _dev(omega, torch.float64, "omega"), nm, pf,
                                    len(fr), _dev(out, torch.complex128, "out"), _stream(modes))
     ctx.check(st, "gw_pp_eps_inverse")
+    return out
+
+
+def sigma_static(psi_n, psi_v, n, a_bohr, q, miller, eps_inv=None, want_x=True,
+                 ctx: Optional[Context] = None):
+    """(sigma_x, sigma_sex) [nn][nn] complex128 on the device; sigma_sex is None without eps_inv and
+    sigma_x is None when want_x is False."""
+    import torch
+    m, pm = _host_i32(miller, "g_miller")
+    ng = m.shape[0]
+    qa, pq = _host_f64(q, "q")
+    nn, nv = psi_n.shape[0], psi_v.shape[0]
+    dev = psi_n.device
+    sx = torch.empty((nn, nn), dtype=torch.complex128, device=dev) if want_x else None
+    ss = torch.empty((nn, nn), dtype=torch.complex128, device=dev) if eps_inv is not None else None
+    ctx = ctx or context(dev.index)
+    st = ctx.lib.gw_sigma_static(ctx.handle, _dev(psi_n, torch.complex64, "psi_n"), nn,
+                                 _dev(psi_v, torch.complex64, "psi_v"), nv, _grid(n, a_bohr), pq, pm, ng,
+                                 _dev(eps_inv, torch.complex128, "eps_inv") if eps_inv is not None else None,
+                                 _dev(sx, torch.complex128, "sigma_x") if sx is not None else None,
+                                 _dev(ss, torch.complex128, "sigma_sex") if ss is not None else None, _stream(psi_n))
+    ctx.check(st, "gw_sigma_static")
+    return sx, ss
+
+
+def sigma_sex_modes(psi_n, psi_v, n, miller, modes, sigma, ctx: Optional[Context] = None):
+    """Screened exchange [nn][nn] complex128 from the plasmon-pole modes (eigen form)."""
+    import torch
+    m, pm = _host_i32(miller, "g_miller")
+    ng = m.shape[0]
+    nn, nv = psi_n.shape[0], psi_v.shape[0]
+    out = torch.empty((nn, nn), dtype=torch.complex128, device=psi_n.device)
+    ctx = ctx or context(psi_n.device.index)
+    st = ctx.lib.gw_sigma_sex_modes(ctx.handle, _dev(psi_n, torch.complex64, "psi_n"), nn,
+                                    _dev(psi_v, torch.complex64, "psi_v"), nv, _grid(n, 1.0), pm, ng,
+                                    _dev(modes, torch.complex128, "modes"), _dev(sigma, torch.float64, "sigma"),
+                                    modes.shape[1], _dev(out, torch.complex128, "sigma_sex"), _stream(psi_n))
+    ctx.check(st, "gw_sigma_sex_modes")
     return out
 
 

@@ -211,7 +211,7 @@ void build_sphere_plan(gw_grid g, const int *miller, int ng, SpherePlan &p) {
 
 // One 3-D transform over the row index of `in` ([nr][B], row stride ld_in) to `out` ([ng][B],
 // row stride ld_out), in column chunks of at most bc.
-static hipError_t transform_rows(const SpherePlan &p, int sign, const float2 *in, long long ld_in, int B, float2 *out,
+hipError_t transform_rows(const SpherePlan &p, int sign, const float2 *in, long long ld_in, int B, float2 *out,
                                  long long ld_out, float2 *a1, float2 *a2, int bc, const int *dA, const int *dB,
                                  const int *dC, hipStream_t s) {
   for (int b0 = 0; b0 < B; b0 += bc) {
@@ -238,6 +238,21 @@ hipError_t enqueue_sphere_transform(const SpherePlan &p, const SphereBuffers &b,
   return launch_transpose_c64(b.q, p_gg, ng, ng, ng, ng, s);
 }
 
+int upload_plan(gw_ctx *ctx, gw_grid g, const int *miller, int ng, int map_slot, SpherePlan &p, int **dA, int **dB,
+                int **dC, hipStream_t s) {
+  build_sphere_plan(g, miller, ng, p);
+  const size_t nA = p.mapA.size(), nB = p.mapB.size(), nC = p.mapC.size();
+  void *maps;
+  GW_STATUS(ws_get(ctx, map_slot, (nA + nB + nC) * sizeof(int), &maps, s));
+  *dA = (int *)maps;
+  *dB = *dA + nA;
+  *dC = *dB + nB;
+  GW_HIP(ctx, hipMemcpyAsync(*dA, p.mapA.data(), nA * sizeof(int), hipMemcpyHostToDevice, s));
+  GW_HIP(ctx, hipMemcpyAsync(*dB, p.mapB.data(), nB * sizeof(int), hipMemcpyHostToDevice, s));
+  GW_HIP(ctx, hipMemcpyAsync(*dC, p.mapC.data(), nC * sizeof(int), hipMemcpyHostToDevice, s));
+  return GW_OK;
+}
+
 }  // namespace gwi
 
 namespace {
@@ -245,20 +260,15 @@ namespace {
 int sphere_transform_impl(gw_ctx *ctx, const float2 *p_rr, gw_grid g, const int *miller, int ng, float2 *p_gg,
                           hipStream_t s) {
   SpherePlan plan;
-  build_sphere_plan(g, miller, ng, plan);
+  int *dA, *dB, *dC;
+  GW_STATUS(upload_plan(ctx, g, miller, ng, WS_FFT_MAP, plan, &dA, &dB, &dC, s));
   const int nr = g.n1 * g.n2 * g.n3;
-  void *a1, *a2, *maps, *ph, *pht, *q;
+  void *a1, *a2, *ph, *pht, *q;
   GW_STATUS(ws_get(ctx, WS_FFT_A, plan.a1_elems * sizeof(float2), &a1, s));
   GW_STATUS(ws_get(ctx, WS_FFT_B, plan.a2_elems * sizeof(float2), &a2, s));
-  const size_t nA = plan.mapA.size(), nB = plan.mapB.size(), nC = plan.mapC.size();
-  GW_STATUS(ws_get(ctx, WS_FFT_MAP, (nA + nB + nC) * sizeof(int), &maps, s));
   GW_STATUS(ws_get(ctx, WS_COUNT_BASE + 0, (size_t)ng * nr * sizeof(float2), &ph, s));
   GW_STATUS(ws_get(ctx, WS_COUNT_BASE + 1, (size_t)ng * nr * sizeof(float2), &pht, s));
   GW_STATUS(ws_get(ctx, WS_PGG_T, (size_t)ng * ng * sizeof(float2), &q, s));
-  int *dA = (int *)maps, *dB = dA + nA, *dC = dB + nB;
-  GW_HIP(ctx, hipMemcpyAsync(dA, plan.mapA.data(), nA * sizeof(int), hipMemcpyHostToDevice, s));
-  GW_HIP(ctx, hipMemcpyAsync(dB, plan.mapB.data(), nB * sizeof(int), hipMemcpyHostToDevice, s));
-  GW_HIP(ctx, hipMemcpyAsync(dC, plan.mapC.data(), nC * sizeof(int), hipMemcpyHostToDevice, s));
   SphereBuffers b{(float2 *)a1, (float2 *)a2, (float2 *)ph, (float2 *)pht, (float2 *)q, dA, dB, dC};
   GW_HIP(ctx, enqueue_sphere_transform(plan, b, p_rr, p_gg, s));
   return GW_OK;
@@ -465,21 +475,16 @@ int gw_orbitals_to_grid(gw_ctx *ctx, const gw_c32 *coeff, int nb, int npw, gw_gr
   hipStream_t s = as_stream(stream);
   const int nr = (int)nrl;
   SpherePlan p;
-  build_sphere_plan(grid, pw_miller, npw, p);
+  int *dA, *dB, *dC;
+  GW_STATUS(upload_plan(ctx, grid, pw_miller, npw, WS_ORB_MAP, p, &dA, &dB, &dC, s));
   // band chunk: the largest intermediate ([nr][w]) stays near 1 GiB
   const int w = (int)std::min<long long>(nb, std::max<long long>(64, (1LL << 27) / nr));
   const size_t rows1 = (size_t)p.n1 * p.n2 * p.m3count, rows2 = (size_t)p.n1 * p.npair;
-  void *ct, *a1, *a2, *rt, *maps;
+  void *ct, *a1, *a2, *rt;
   GW_STATUS(ws_get(ctx, WS_ORB_T, (size_t)npw * w * sizeof(float2), &ct, s));
   GW_STATUS(ws_get(ctx, WS_ORB_A1, rows1 * w * sizeof(float2), &a1, s));
   GW_STATUS(ws_get(ctx, WS_ORB_A2, rows2 * w * sizeof(float2), &a2, s));
   GW_STATUS(ws_get(ctx, WS_ORB_R, (size_t)nr * w * sizeof(float2), &rt, s));
-  const size_t nA = p.mapA.size(), nB = p.mapB.size(), nC = p.mapC.size();
-  GW_STATUS(ws_get(ctx, WS_ORB_MAP, (nA + nB + nC) * sizeof(int), &maps, s));
-  int *dA = (int *)maps, *dB = dA + nA, *dC = dB + nB;
-  GW_HIP(ctx, hipMemcpyAsync(dA, p.mapA.data(), nA * sizeof(int), hipMemcpyHostToDevice, s));
-  GW_HIP(ctx, hipMemcpyAsync(dB, p.mapB.data(), nB * sizeof(int), hipMemcpyHostToDevice, s));
-  GW_HIP(ctx, hipMemcpyAsync(dC, p.mapC.data(), nC * sizeof(int), hipMemcpyHostToDevice, s));
   const float scale = (float)(1.0 / std::sqrt((double)nr));
   const float2 *c = (const float2 *)coeff;
   float2 *out = (float2 *)psi;
@@ -647,4 +652,5 @@ int api_check_grid(gw_ctx *ctx, gw_grid g) { return check_grid(ctx, g); }
 int api_grid_supported(gw_ctx *ctx, gw_grid g) { return grid_supported(ctx, g); }
 int api_begin(gw_ctx *ctx) { return begin(ctx); }
 void api_set_err(gw_ctx *ctx, const char *msg) { set_err(ctx, "%s", msg); }
+int api_device(gw_ctx *ctx) { return ctx->device; }
 }  // namespace gwi

@@ -120,6 +120,16 @@ hipError_t launch_pp_weight(const double2 *modes, int ng, int nm, const double *
 hipError_t launch_pp_finish(double2 *e, const double2 *ei_static, const double *sv, int ng, hipStream_t s);
 hipError_t launch_sqrtv(const int *miller, int ng, double q0, double q1, double q2, double a_bohr, double *sv,
                         hipStream_t s);
+// Static self-energy kernels (sigma.hip)
+hipError_t launch_fill_f32(float *p, int n, float v, hipStream_t s);
+hipError_t launch_conj_upcast(const float2 *in, size_t n, double2 *out, hipStream_t s);
+hipError_t launch_contract_conj(const float2 *a, const float2 *b, int ng, int nv, long long ld, const double *sv,
+                                double scale, int nn, double2 *out, hipStream_t s);
+hipError_t launch_contract_t(const float2 *a, const double2 *t, int ng, int nv, long long ld, double scale, int nn,
+                             double2 *out, hipStream_t s);
+hipError_t launch_zeta(const float2 *f, int ng, int npair, const double2 *modes, int nm, double2 *zeta, hipStream_t s);
+hipError_t launch_contract_modes(const double2 *zeta, int nm, int nv, int nn, const double *sigma, double2 *out,
+                                 hipStream_t s);
 // Newton iteration for the inverse: workspace of newton_ws_bytes(n) holds x, t, xn and the scalars.
 size_t newton_ws_bytes(int n);
 hipError_t newton_start(const double2 *a, int n, double2 *x, double2 *t, double *scratch, hipStream_t s);
@@ -159,6 +169,15 @@ struct SphereBuffers {
 };
 hipError_t enqueue_sphere_transform(const SpherePlan &p, const SphereBuffers &b, const float2 *p_rr, float2 *p_gg,
                                     hipStream_t s);
+// One 3-D transform over the row index of `in` ([nr][B], row stride ld_in) to the sphere rows of
+// `out` ([ng][B], row stride ld_out), in column chunks of at most bc (a1, a2 hold rowsA*bc and
+// n1*npair*bc elements).
+hipError_t transform_rows(const SpherePlan &p, int sign, const float2 *in, long long ld_in, int B, float2 *out,
+                          long long ld_out, float2 *a1, float2 *a2, int bc, const int *dA, const int *dB,
+                          const int *dC, hipStream_t s);
+// Build the sphere plan and copy its maps into workspace slot `map_slot`.
+int upload_plan(gw_ctx *ctx, gw_grid g, const int *miller, int ng, int map_slot, SpherePlan &p, int **dA, int **dB,
+                int **dC, hipStream_t s);
 
 // ---- shared host helpers of gw_api.cpp used by the batched path ---------------------------------
 int api_ws_get(gw_ctx *ctx, int slot, size_t bytes, void **out, hipStream_t s);
@@ -169,6 +188,7 @@ int api_check_grid(gw_ctx *ctx, gw_grid g);
 int api_grid_supported(gw_ctx *ctx, gw_grid g);
 int api_begin(gw_ctx *ctx);
 void api_set_err(gw_ctx *ctx, const char *msg);
+int api_device(gw_ctx *ctx);
 
 // ---- tile autotuner --------------------------------------------------------------------------------
 // Tuned tile for (nr, nv, nc, precision) on the context's device, or -1 if none is cached.

@@ -158,6 +158,13 @@ def test_dry_run_other_entry_points(gw):
     assert lib.gw_pp_eps_inverse(h, vp(), len(m), grid, pq, pm, vp(), vp(), vp(), 4, pfr, 0, vp(), None) == 1
     frn, pfrn = f64([np.nan])
     assert lib.gw_pp_eps_inverse(h, vp(), len(m), grid, pq, pm, vp(), vp(), vp(), 4, pfrn, 1, vp(), None) == 1
+    # static self-energy
+    sg = lambda **kw: lib.gw_sigma_static(h, vp(), kw.get("nn", 4), vp(), kw.get("nv", 3), grid, pq, pm, len(m),
+                                          kw.get("ei", vp()), kw.get("sx", vp()), kw.get("ss", vp()), None)
+    assert sg() == 0 and sg(ei=None, ss=None) == 0 and sg(sx=None) == 0
+    assert sg(sx=None, ss=None) == 1 and sg(ei=None) == 1 and sg(nn=0) == 1 and sg(nn=257) == 1 and sg(nv=0) == 1
+    assert lib.gw_sigma_sex_modes(h, vp(), 4, vp(), 3, grid, pm, len(m), vp(), vp(), 5, vp(), None) == 0
+    assert lib.gw_sigma_sex_modes(h, vp(), 4, vp(), 3, grid, pm, len(m), vp(), vp(), 0, vp(), None) == 1
     # Newton iteration arguments
     its = C.c_int(-1)
     assert lib.gw_newton_inverse(h, vp(), 10, 1e-11, 50, vp(), C.byref(its), None, None) == 0 and its.value == 0
