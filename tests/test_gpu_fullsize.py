@@ -9,6 +9,8 @@ import pytest
 
 import gwsynth as gs
 import oracle as orc
+from oracle import pp_oracle as pp
+from oracle import sigma_oracle as so
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -70,3 +72,22 @@ def test_production_size(setup, prec, tol):
         e_n = orc.rel_f(xn.cpu().numpy(), ei_ref)
         print(f"Newton at N_g = {len(s.miller)}: {it} iterations, last change {hist[-1]:.1e}, rel_F vs LU {e_n:.2e}")
         assert hist[-1] < 1e-11 and e_n < 1e-10
+        # plasmon-pole modes and the static exchange terms at the same size
+        sv = orc.coulomb_sqrt(s.n, s.a_bohr, s.q, s.miller)
+        e = einv.cpu().numpy()
+        pv64 = setup["pv"].cpu().numpy()
+        sig, om, modes, its, res = gw.plasmon_pole(einv, s.n, s.a_bohr, s.q, s.miller, setup["pv"], 1.0, 8)
+        s_ref, o_ref, a_ref = pp.plasmon_pole(e, s.n, s.a_bohr, s.q, s.miller, sv, pv64, 1.0, 8)
+        e_sig = np.max(np.abs(sig.cpu().numpy() - s_ref)) / abs(s_ref[0])
+        e_om = np.max(np.abs(om.cpu().numpy() - o_ref) / o_ref)
+        ov = np.abs(np.sum(np.conj(a_ref) * modes.cpu().numpy(), axis=0))
+        print(f"plasmon pole at N_g = {len(sv)}: {its} iterations, sigma {e_sig:.1e}, omega {e_om:.1e}, "
+              f"1-overlap {np.max(1 - ov):.1e}", flush=True)
+        assert e_sig < 1e-10 and e_om < 1e-7 and np.min(ov) > 1 - 1e-7
+        bands = torch.cat([setup["pv"][-8:], setup["pc"][:8]]).contiguous()
+        sx, ss = gw.sigma_static(bands, setup["pv"], s.n, s.a_bohr, s.q, s.miller, eps_inv=einv)
+        ft = so.pair_transform(bands.cpu().numpy(), pv64, s.n, s.miller)
+        ex = orc.rel_f(sx.cpu().numpy(), so.sigma_x(ft, sv))
+        es = orc.rel_f(ss.cpu().numpy(), so.sigma_sex(ft, pp.screening_part(e, sv)))
+        print(f"static exchange, 16 bands x 128 occupied: sigma_x rel_F {ex:.1e}, sigma_sex rel_F {es:.1e}")
+        assert ex < 1e-6 and es < 1e-6
