@@ -8,6 +8,8 @@
 // zgemm: C = alpha * op(A) op(B) + beta * C for complex128, op = identity or conjugate
 // transpose, on v_mfma_f64_16x16x4f64.  Complex products use real MFMA with k' = (k, re/im):
 //   Re C += [Re A, Im A] . [Re B; -Im B],   Im C += [Re A, Im A] . [Im B; Re B].
+#include <algorithm>
+
 #include "gw_internal.h"
 
 namespace gwi {
@@ -20,8 +22,15 @@ constexpr int GK = 8;     // complex k per stage
 __global__ __launch_bounds__(256) void zgemm_kernel(int M, int N, int K, const double2 *__restrict__ A, long long lda,
                                                     int transA, const double2 *__restrict__ B, long long ldb,
                                                     int transB, double2 *__restrict__ C, long long ldc, double alpha,
-                                                    double beta, int lower_only, int tri_k) {
+                                                    double beta, int lower_only, int tri_k, int kchunk,
+                                                    long long cz_stride) {
   const int row0 = blockIdx.y * GT, col0 = blockIdx.x * GT;
+  // split K: workgroup z takes k in [z kchunk, (z+1) kchunk) and writes its own partial C
+  int kend = K;
+  if (kchunk > 0) {
+    C += blockIdx.z * cz_stride;
+    kend = min(K, (int)(blockIdx.z + 1) * kchunk);
+  }
   if (lower_only && col0 >= row0 + GT) return;
   __shared__ double sA[GK][2][GT];
   __shared__ double sX[GK][2][GT];
@@ -36,10 +45,10 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int M, int N, int K, const d
 #pragma unroll
       for (int e = 0; e < 4; ++e) { accR[a][b][e] = 0.0; accI[a][b][e] = 0.0; }
 
-  int kbeg = 0;
+  int kbeg = kchunk > 0 ? (int)blockIdx.z * kchunk : 0;
   if (tri_k) kbeg = (max(row0, col0) / GK) * GK;
   const int kl = lane >> 4, li = lane & 15;
-  for (int k0 = kbeg; k0 < K; k0 += GK) {
+  for (int k0 = kbeg; k0 < kend; k0 += GK) {
 #pragma unroll
     for (int it = 0; it < (GT * GK) / 256; ++it) {
       const int idx = tid + it * 256;
@@ -47,7 +56,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int M, int N, int K, const d
       int r, kk;
       if (transA) { r = idx % GT; kk = idx / GT; } else { r = idx / GK; kk = idx % GK; }
       double2 va = make_double2(0.0, 0.0);
-      if (row0 + r < M && k0 + kk < K) {
+      if (row0 + r < M && k0 + kk < kend) {
         if (transA) { va = A[(long long)(k0 + kk) * lda + row0 + r]; va.y = -va.y; }
         else va = A[(long long)(row0 + r) * lda + k0 + kk];
       }
@@ -57,7 +66,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int M, int N, int K, const d
       int c;
       if (transB) { c = idx / GK; kk = idx % GK; } else { c = idx % GT; kk = idx / GT; }
       double2 vb = make_double2(0.0, 0.0);
-      if (col0 + c < N && k0 + kk < K) {
+      if (col0 + c < N && k0 + kk < kend) {
         if (transB) { vb = B[(long long)(col0 + c) * ldb + k0 + kk]; vb.y = -vb.y; }
         else vb = B[(long long)(k0 + kk) * ldb + col0 + c];
       }
@@ -108,7 +117,55 @@ static hipError_t zgemm(int M, int N, int K, const double2 *A, long long lda, in
   if (M <= 0 || N <= 0) return hipSuccess;
   dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
   hipLaunchKernelGGL(zgemm_kernel, grid, dim3(256), 0, s, M, N, K, A, lda, transA, B, ldb, transB, C, ldc, alpha,
-                     beta, lower_only, tri_k);
+                     beta, lower_only, tri_k, 0, 0LL);
+  return hipGetLastError();
+}
+
+// c[i][j] = alpha sum_z w[z][i][j] + beta c[i][j]   (w packed [kz][M][N])
+__global__ void splitk_reduce_kernel(const double2 *__restrict__ w, int kz, int M, int N, double2 *__restrict__ c,
+                                     long long ldc, double alpha, double beta) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)M * N) return;
+  const int i = (int)(idx / N), j = (int)(idx % N);
+  double re = 0.0, im = 0.0;
+  for (int z = 0; z < kz; ++z) {
+    const double2 v = w[(size_t)z * M * N + idx];
+    re += v.x;
+    im += v.y;
+  }
+  double2 *d = c + (long long)i * ldc + j;
+  double2 out = make_double2(alpha * re, alpha * im);
+  if (beta != 0.0) {
+    const double2 o = *d;
+    out.x += beta * o.x;
+    out.y += beta * o.y;
+  }
+  *d = out;
+}
+
+size_t zgemm_splitk_ws_elems(int M, int N, int K) {
+  const long long tiles = (long long)((M + GT - 1) / GT) * ((N + GT - 1) / GT);
+  if (tiles >= 256 || K < 4 * GK) return 0;
+  const int kz = (int)std::min<long long>(std::max<long long>(1, 512 / tiles), (K + 255) / 256);
+  return kz > 1 ? (size_t)kz * M * N : 0;
+}
+
+hipError_t launch_zgemm_splitk(int M, int N, int K, const double2 *A, long long lda, int transA, const double2 *B,
+                               long long ldb, int transB, double2 *C, long long ldc, double alpha, double beta,
+                               double2 *ws, size_t ws_elems, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const size_t need = zgemm_splitk_ws_elems(M, N, K);
+  if (need == 0 || ws == nullptr || ws_elems < need)
+    return zgemm(M, N, K, A, lda, transA, B, ldb, transB, C, ldc, alpha, beta, 0, 0, s);
+  const int kz = (int)(need / ((size_t)M * N));
+  int kchunk = (K + kz - 1) / kz;
+  kchunk = (kchunk + GK - 1) / GK * GK;
+  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, kz);
+  // each z slice writes every (i, j) of its partial (padded k past kend reads zero), so ws needs no clearing
+  hipLaunchKernelGGL(zgemm_kernel, grid, dim3(256), 0, s, M, N, K, A, lda, transA, B, ldb, transB, ws, (long long)N,
+                     1.0, 0.0, 0, 0, kchunk, (long long)M * N);
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)(((size_t)M * N + 255) / 256)), dim3(256), 0, s, ws, kz, M,
+                     N, C, ldc, alpha, beta);
   return hipGetLastError();
 }
 

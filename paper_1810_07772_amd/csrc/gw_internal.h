@@ -101,6 +101,13 @@ hipError_t launch_fill_int(int *p, int value, hipStream_t s);
 hipError_t launch_zgemm(int M, int N, int K, const double2 *A, long long lda, int transA, const double2 *B,
                         long long ldb, int transB, double2 *C, long long ldc, double alpha, double beta,
                         hipStream_t s);
+// The same for thin outputs (fewer than 256 output tiles): K is split over workgroups into partial
+// products in ws (zgemm_splitk_ws_elems(M, N, K) complex128 elements; 0 means no split is used) and
+// summed by a second kernel.  Falls back to the plain product when ws is too small.
+size_t zgemm_splitk_ws_elems(int M, int N, int K);
+hipError_t launch_zgemm_splitk(int M, int N, int K, const double2 *A, long long lda, int transA, const double2 *B,
+                               long long ldb, int transB, double2 *C, long long ldc, double alpha, double beta,
+                               double2 *ws, size_t ws_elems, hipStream_t s);
 // Plasmon-pole kernels (pp.hip)
 hipError_t launch_density(const float2 *psi, int nv, int nr, double occ, double2 *rho, hipStream_t s);
 hipError_t launch_density_transform(double2 *rho, double2 *tmp, int n1, int n2, int n3, hipStream_t s);

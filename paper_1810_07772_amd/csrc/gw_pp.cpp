@@ -24,12 +24,14 @@ constexpr int kBlock = 32;      // subspace size (the Jacobi kernel's limit)
 constexpr int kMaxModes = 24;   // at least 8 guard vectors beyond the wanted modes
 
 enum {
-  PP_MILLER = 40, PP_SQRTV, PP_RHO, PP_RHO_T, PP_S, PP_M, PP_X, PP_Y, PP_W, PP_T, PP_SMALL, PP_B
+  PP_MILLER = 40, PP_SQRTV, PP_RHO, PP_RHO_T, PP_S, PP_M, PP_X, PP_Y, PP_W, PP_T, PP_SMALL, PP_B, PP_SPLITK
 };
 
 struct Small {            // b x b matrices and eigenvalues of the iteration
   double2 *h, *z, *g, *u;
   double *theta, *lam, *res;
+  double2 *ws;             // split-K partial products of the thin products
+  size_t ws_elems;
 };
 
 int upload_sphere(gw_ctx *ctx, const int *miller, int ng, const double *q, double a_bohr, int **dm, double **dsv,
@@ -47,7 +49,7 @@ int upload_sphere(gw_ctx *ctx, const int *miller, int ng, const double *q, doubl
 // x = orthonormal basis of the columns of w (w is overwritten by its column-normalised copy)
 int orthonormalize(gw_ctx *ctx, double2 *w, int ng, int b, const Small &sm, double2 *x, hipStream_t s) {
   GWX_HIP(ctx, launch_col_normalize(w, ng, b, b, s));
-  GWX_HIP(ctx, launch_zgemm(b, b, ng, w, b, 1, w, b, 0, sm.g, b, 1.0, 0.0, s));
+  GWX_HIP(ctx, launch_zgemm_splitk(b, b, ng, w, b, 1, w, b, 0, sm.g, b, 1.0, 0.0, sm.ws, sm.ws_elems, s));
   GWX_HIP(ctx, launch_herm_jacobi(sm.g, b, b, sm.lam, sm.u, b, s));
   GWX_HIP(ctx, launch_svqb_scale(sm.u, sm.lam, b, 1e-14, s));
   GWX_HIP(ctx, launch_zgemm(ng, b, b, w, b, 0, sm.u, b, 0, x, b, 1.0, 0.0, s));
@@ -111,14 +113,22 @@ int gw_plasmon_pole(gw_ctx *ctx, const gw_c64 *eps_inv, int ng, gw_grid grid, co
   sm.theta = (double *)(sm.u + bb);
   sm.lam = sm.theta + b;
   sm.res = sm.lam + b;
+  sm.ws_elems = std::max({zgemm_splitk_ws_elems(ng, b, ng), zgemm_splitk_ws_elems(b, b, ng),
+                          zgemm_splitk_ws_elems(ng, n_modes, ng)});
+  sm.ws = nullptr;
+  if (sm.ws_elems) {
+    void *w;
+    GWX_STATUS(api_ws_get(ctx, PP_SPLITK, sm.ws_elems * sizeof(double2), &w, s));
+    sm.ws = (double2 *)w;
+  }
   double2 *X = (double2 *)xp, *Y = (double2 *)yp, *W = (double2 *)wp, *T = (double2 *)tp;
   GWX_HIP(ctx, launch_start_block(T, ng, b, 0x5eedULL, s));
   GWX_STATUS(orthonormalize(ctx, T, ng, b, sm, X, s));
   double res = INFINITY;
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
-    GWX_HIP(ctx, launch_zgemm(ng, b, ng, S, ng, 0, X, b, 0, Y, b, -1.0, 0.0, s));   // Y = -S X
-    GWX_HIP(ctx, launch_zgemm(b, b, ng, X, b, 1, Y, b, 0, sm.h, b, 1.0, 0.0, s));   // H = X^H Y
+    GWX_HIP(ctx, launch_zgemm_splitk(ng, b, ng, S, ng, 0, X, b, 0, Y, b, -1.0, 0.0, sm.ws, sm.ws_elems, s));  // -S X
+    GWX_HIP(ctx, launch_zgemm_splitk(b, b, ng, X, b, 1, Y, b, 0, sm.h, b, 1.0, 0.0, sm.ws, sm.ws_elems, s));  // X^H Y
     GWX_HIP(ctx, launch_herm_jacobi(sm.h, b, b, sm.theta, sm.z, b, s));
     GWX_HIP(ctx, launch_zgemm(ng, b, b, X, b, 0, sm.z, b, 0, W, b, 1.0, 0.0, s));   // Ritz vectors
     GWX_HIP(ctx, launch_zgemm(ng, b, b, Y, b, 0, sm.z, b, 0, T, b, 1.0, 0.0, s));   // -S times them
@@ -132,7 +142,7 @@ int gw_plasmon_pole(gw_ctx *ctx, const gw_c64 *eps_inv, int ng, gw_grid grid, co
   *iterations = std::min(it, max_iter);
   if (residual) *residual = res;
   // frequencies from the sum rule: t = M A, omega_a^2 = Re(a^H t_a) / theta_a
-  GWX_HIP(ctx, launch_zgemm(ng, n_modes, ng, M, ng, 0, W, b, 0, Y, n_modes, 1.0, 0.0, s));
+  GWX_HIP(ctx, launch_zgemm_splitk(ng, n_modes, ng, M, ng, 0, W, b, 0, Y, n_modes, 1.0, 0.0, sm.ws, sm.ws_elems, s));
   GWX_HIP(ctx, launch_pp_frequency(W, b, Y, n_modes, ng, sm.theta, n_modes, sigma, omega, s));
   GWX_HIP(ctx, hipMemcpy2DAsync(modes, (size_t)n_modes * sizeof(double2), W, (size_t)b * sizeof(double2),
                                 (size_t)n_modes * sizeof(double2), ng, hipMemcpyDeviceToDevice, s));
