@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <limits>
@@ -203,7 +204,10 @@ void build_sphere_plan(gw_grid g, const int *miller, int ng, SpherePlan &p) {
   // column chunk of the row passes so that the first intermediate stays near 1 GiB
   const long long nr = (long long)g.n1 * g.n2 * g.n3;
   const long long rowsA = (long long)g.n1 * g.n2 * p.m3count;
+  // (smaller chunks that keep the intermediates in the 256 MB last-level cache measured slower: every
+  // pass already streams near HBM speed, and more chunks add launches)
   long long bc = std::max<long long>(256, std::min<long long>(nr, (1LL << 27) / std::max<long long>(1, rowsA)));
+  bc = std::min<long long>(nr, (bc + 255) / 256 * 256);      // whole 256-lane blocks
   p.bc = (int)std::min<long long>(bc, nr);
   p.a1_elems = (size_t)rowsA * p.bc;
   p.a2_elems = (size_t)g.n1 * p.npair * p.bc;
