@@ -595,8 +595,6 @@ int gw_newton_inverse(gw_ctx *ctx, const gw_c64 *a, int n, double tol, int max_i
   double2 *x = (double2 *)w, *t = x + nn, *xn = t + nn;
   double *sc = (double *)(xn + nn);
   GW_HIP(ctx, newton_start((const double2 *)a, n, x, t, sc, s));
-  double *host = (double *)ctx->pivot_host;     // pinned scratch (8 bytes are enough for one double)
-  (void)host;
   double diff = 0.0;
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
