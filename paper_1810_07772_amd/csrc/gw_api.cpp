@@ -299,7 +299,7 @@ int polarizability_r_impl(gw_ctx *ctx, const float2 *psi_v, int nv, const float2
   int *bexp = nullptr;
   if (o.precision == GW_SPLIT_FP16_SCALED) {
     void *b;
-    GW_STATUS(ws_get(ctx, WS_BSCALE, (size_t)(nv + nv + nc) * sizeof(int), &b, s));
+    GW_STATUS(ws_get(ctx, WS_BSCALE, band_exp_ints(nv, nc) * sizeof(int), &b, s));
     bexp = (int *)b;
     GW_HIP(ctx, launch_band_exponents(psi_v, nv, psi_c, nc, nr, scale, scale_ld(nc), bexp, s));
   }

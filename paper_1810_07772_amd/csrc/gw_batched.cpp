@@ -123,7 +123,7 @@ int autotune_impl(gw_ctx *ctx, const float2 *psi_v, int nv, const float2 *psi_c,
   void *eb, *sb, *bx;
   GWX_STATUS(api_ws_get(ctx, WS_ENERGY, (size_t)(nv + nc) * sizeof(double), &eb, s));
   GWX_STATUS(api_ws_get(ctx, WS_SCALE, (size_t)nv * ldsc * sizeof(float), &sb, s));
-  GWX_STATUS(api_ws_get(ctx, WS_BSCALE, (size_t)(2 * nv + nc) * sizeof(int), &bx, s));
+  GWX_STATUS(api_ws_get(ctx, WS_BSCALE, band_exp_ints(nv, nc) * sizeof(int), &bx, s));
   double *de = (double *)eb;
   GWX_HIP(ctx, hipMemcpyAsync(de, e_v, nt * sizeof(double), hipMemcpyHostToDevice, s));
   GWX_HIP(ctx, hipMemcpyAsync(de + nt, e_c, nc * sizeof(double), hipMemcpyHostToDevice, s));
@@ -266,7 +266,7 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
     const SpherePlan &pl = plans[j];
     void *p[kJobSlots];
     const size_t bytes[kJobSlots] = {(size_t)(nv + nc) * sizeof(double), (size_t)nv * scale_ld(nc) * sizeof(float),
-                                     (size_t)(2 * nv + nc) * sizeof(int),
+                                     band_exp_ints(nv, nc) * sizeof(int),
                                      (pl.mapA.size() + pl.mapB.size() + pl.mapC.size()) * sizeof(int),
                                      (size_t)ng * 3 * sizeof(int), (size_t)ng * sizeof(double)};
     for (int k = 0; k < kJobSlots; ++k) {

@@ -73,6 +73,8 @@ hipError_t launch_herk(int precision, int tile, const float2 *psi_v, const float
                        const int *band_exp, float2 *p, int nr, int nv, int nc, int accumulate, hipStream_t s);
 hipError_t launch_band_exponents(const float2 *psi_v, int nv, const float2 *psi_c, int nc, int nr,
                                  const float *scale, int ldsc, int *band_exp, hipStream_t s);
+// ints needed by launch_band_exponents' buffer (exponents, band order, sorted exponents, row maxima)
+size_t band_exp_ints(int nv, int nc);
 
 // FFT helpers.
 bool fft_size_supported(int n);

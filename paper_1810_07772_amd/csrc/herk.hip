@@ -83,6 +83,35 @@ __device__ __forceinline__ void store_tile(float2 *__restrict__ P, int nr, int I
       }
 }
 
+// Partial-sum store of the two-level sum: adds -acc to the tile and conj(-acc) to its mirror
+// (off-diagonal tiles) with atomic adds that return nothing, so no old values are loaded into
+// registers.  Every element has exactly one writer, so the result does not depend on timing.
+__device__ __forceinline__ void add_tile(float2 *__restrict__ P, int nr, int I0, int J0, bool mirror,
+                                         const f32x16 (&re)[2][2], const f32x16 (&im)[2][2], int wr, int wc,
+                                         int lane) {
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int i = (e & 3) + 8 * (e >> 2) + 4 * (lane >> 5);
+        const int j = lane & 31;
+        const int row = I0 + wr * 64 + rb * 32 + i;
+        const int col = J0 + wc * 64 + cb * 32 + j;
+        if (row < nr && col < nr) {
+          float *d = reinterpret_cast<float *>(P + (size_t)row * nr + col);
+          __hip_atomic_fetch_add(d, -re[rb][cb][e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(d + 1, -im[rb][cb][e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (mirror) {
+            float *m = reinterpret_cast<float *>(P + (size_t)col * nr + row);
+            __hip_atomic_fetch_add(m, -re[rb][cb][e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(m + 1, im[rb][cb][e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+      }
+}
+
 // ---------------------------------------------------------------------------------------------
 // FP32 variant
 // ---------------------------------------------------------------------------------------------
@@ -397,24 +426,58 @@ __global__ __launch_bounds__(NTHR, 1) void herk_split_kernel(const float2 *__res
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
 // (a, b) -> one word holding (bf16 RNE(a), bf16 RNE(b)); gfx950 does this in one instruction.
 __device__ __forceinline__ unsigned pk_bf16(float a, float b) {
   const f32x2 v = {a, b};
   return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
 }
 
-template <int KW, bool PRIO>
+// hi = RNE(a, b) packed in one word, lo = RNE of the remainders, for BF16 or FP16 halves.
+template <typename T> struct NarrowSplit;
+template <> struct NarrowSplit<__bf16> {
+  static __device__ __forceinline__ void split(float a, float b, unsigned &hi, unsigned &lo) {
+    hi = pk_bf16(a, b);
+    lo = pk_bf16(a - __builtin_bit_cast(float, hi << 16), b - __builtin_bit_cast(float, hi & 0xffff0000u));
+  }
+};
+template <> struct NarrowSplit<_Float16> {
+  static __device__ __forceinline__ void split(float a, float b, unsigned &hi, unsigned &lo) {
+    const f32x2 v = {a, b};
+    const f16x2 h = __builtin_convertvector(v, f16x2);
+    const f32x2 r = {a - (float)h[0], b - (float)h[1]};
+    hi = __builtin_bit_cast(unsigned, h);
+    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(r, f16x2));
+  }
+};
+
+// Two-level sum: every FOLD_PAIRS pairs of K the consumers add their partial sums into the tile of
+// P and its mirror and restart from zero, so FP32 rounding in the accumulators grows with the block
+// length instead of with K.  The first block is stored (unless accumulating into P), later blocks
+// are added.
+constexpr int FOLD_PAIRS = 32768;
+
+// SCALED (FP16): band v's pair products carry 2^{e_v}, so its products carry 2^{2 e_v}.  The bands
+// run in the order `order` (sorted by exponent, from launch_band_exponents), and the accumulators
+// are multiplied by the exact power of two 2^{2(e_new - e_old)} whenever the exponent changes
+// between stages (a few times per unoccupied chunk), and by 2^{-2 e_last} at the end: the same
+// per-band scale as a fold per band, without a second accumulator set.
+template <typename T, int KW, bool PRIO, bool SCALED>
 __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2 *__restrict__ psi_v,
                                                                      const float2 *__restrict__ psi_c,
                                                                      const float *__restrict__ scale, int ldsc,
+                                                                     const int *__restrict__ band_exp,
                                                                      float2 *__restrict__ P, int nr, int nv, int nc,
                                                                      int ntiles, int accumulate) {
-  typedef bf16x8 vec;
+  typedef typename SplitTraits<T>::vec vec;
   constexpr int SRW = 2 * KW + 8;   // narrow elements per point row (padded against bank conflicts)
-  __shared__ __attribute__((aligned(16))) __bf16 sAh[2][HB][SRW];
-  __shared__ __attribute__((aligned(16))) __bf16 sAl[2][HB][SRW];
-  __shared__ __attribute__((aligned(16))) __bf16 sBh[2][HB][SRW];
-  __shared__ __attribute__((aligned(16))) __bf16 sBl[2][HB][SRW];
+  __shared__ __attribute__((aligned(16))) T sAh[2][HB][SRW];
+  __shared__ __attribute__((aligned(16))) T sAl[2][HB][SRW];
+  __shared__ __attribute__((aligned(16))) T sBh[2][HB][SRW];
+  __shared__ __attribute__((aligned(16))) T sBl[2][HB][SRW];
+  // band order and sorted exponents (SCALED only): see launch_band_exponents
+  const int *order = SCALED ? band_exp + nv : nullptr, *esorted = SCALED ? band_exp + 2 * nv : nullptr;
 
   int bi, bj;
   tile_of(xcd_remap(blockIdx.x, ntiles), bi, bj);
@@ -442,8 +505,14 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
     for (int k = 0; k < KW; ++k) dst[k] = psi_c[(size_t)min(cc * KW + k, nc - 1) * nr + gpt];
   };
   auto load_v = [&](int ch) {                       // psi_v and the scales of stage ch
-    const int v = ch % nv, c0 = (ch / nv) * KW;
+    const int vi = ch % nv, c0 = (ch / nv) * KW;
+    const int v = SCALED ? order[vi] : vi;
     pvv = psi_v[(size_t)v * nr + gpt];
+    if (SCALED) {
+      const float m = ldexpf(1.0f, esorted[vi]);
+      pvv.x *= m;
+      pvv.y *= m;
+    }
     const float *srow = scale + (size_t)v * ldsc + c0;
 #pragma unroll
     for (int k = 0; k < KW; ++k) sc[k] = srow[k];
@@ -459,9 +528,10 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
         const int k = 4 * g + m;
         const float fx = (pvv.x * pc[k].x + pvv.y * pc[k].y) * sc[k];
         const float fy = (pvv.x * pc[k].y - pvv.y * pc[k].x) * sc[k];
-        const unsigned w = pk_bf16(fx, fy);
+        unsigned w, wl;
+        NarrowSplit<T>::split(fx, fy, w, wl);
         hv[m] = w;
-        lv[m] = pk_bf16(fx - __builtin_bit_cast(float, w << 16), fy - __builtin_bit_cast(float, w & 0xffff0000u));
+        lv[m] = wl;
       }
       dh[g] = hv;
       dl[g] = lv;
@@ -507,9 +577,36 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int e = 0; e < 16; ++e) { accR[a][b][e] = 0.f; accI[a][b][e] = 0.f; }
+  // accumulators carry 2^{2e}: back to the true scale
+  auto unscale = [&](int e) {
+    const float f = ldexpf(1.0f, -2 * e);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        accR[a][b] *= f;
+        accI[a][b] *= f;
+      }
+  };
+  constexpr int FOLD_STAGES = FOLD_PAIRS / KW;
+  int nfold = 0;
   __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
+    if (SCALED && ch > 0 && (ch % FOLD_STAGES) != 0) {
+      const int vi = ch % nv;
+      const int d = esorted[vi] - esorted[vi == 0 ? nv - 1 : vi - 1];
+      if (d != 0) {                                        // uniform: every lane reads the same exponents
+        const float f = ldexpf(1.0f, 2 * d);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            accR[a][b] *= f;
+            accI[a][b] *= f;
+          }
+      }
+    }
 #pragma unroll
     for (int g = 0; g < KW / 8; ++g) {
       const int ko = g * 16 + kq * 8;
@@ -523,23 +620,42 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
       const vec bl1 = *reinterpret_cast<const vec *>(&sBl[buf][bc0 + 32][ko]);
       const vec yh0 = rot_neg(bh0), yh1 = rot_neg(bh1), yl0 = rot_neg(bl0), yl1 = rot_neg(bl1);
       // eight independent accumulators per product, so consecutive MFMAs never chain
-#define GW_PROD8(A0, A1, B0, B1, Y0, Y1)                                          \
-  accR[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, B0, accR[0][0], 0, 0, 0); \
-  accI[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, Y0, accI[0][0], 0, 0, 0); \
-  accR[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, B1, accR[0][1], 0, 0, 0); \
-  accI[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, Y1, accI[0][1], 0, 0, 0); \
-  accR[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B0, accR[1][0], 0, 0, 0); \
-  accI[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, Y0, accI[1][0], 0, 0, 0); \
-  accR[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B1, accR[1][1], 0, 0, 0); \
-  accI[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, Y1, accI[1][1], 0, 0, 0);
+#define GW_PROD8(A0, A1, B0, B1, Y0, Y1)                          \
+  accR[0][0] = SplitTraits<T>::mfma(A0, B0, accR[0][0]);           \
+  accI[0][0] = SplitTraits<T>::mfma(A0, Y0, accI[0][0]);           \
+  accR[0][1] = SplitTraits<T>::mfma(A0, B1, accR[0][1]);           \
+  accI[0][1] = SplitTraits<T>::mfma(A0, Y1, accI[0][1]);           \
+  accR[1][0] = SplitTraits<T>::mfma(A1, B0, accR[1][0]);           \
+  accI[1][0] = SplitTraits<T>::mfma(A1, Y0, accI[1][0]);           \
+  accR[1][1] = SplitTraits<T>::mfma(A1, B1, accR[1][1]);           \
+  accI[1][1] = SplitTraits<T>::mfma(A1, Y1, accI[1][1]);
       GW_PROD8(ah0, ah1, bh0, bh1, yh0, yh1)     // hi * hi
       GW_PROD8(ah0, ah1, bl0, bl1, yl0, yl1)     // hi * lo
       GW_PROD8(al0, al1, bh0, bh1, yh0, yh1)     // lo * hi
 #undef GW_PROD8
     }
+    if ((ch + 1) % FOLD_STAGES == 0 && ch + 1 < nch) {
+      // two-level sum: this block's partial goes into the tile, the accumulators restart from zero
+      if (SCALED) unscale(esorted[ch % nv]);
+      // the store addresses do not change between folds; hide that from the compiler, or it keeps
+      // all of them live across the loop and spills
+      int lane_f = lane;
+      asm volatile("" : "+v"(lane_f));
+      if (accumulate || nfold > 0) add_tile(P, nr, I0, J0, bi != bj, accR, accI, wr, wc, lane_f);
+      else store_tile(P, nr, I0, J0, bi != bj, 0, accR, accI, wr, wc, lane_f);
+      ++nfold;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int e = 0; e < 16; ++e) { accR[a][b][e] = 0.f; accI[a][b][e] = 0.f; }
+    }
     __syncthreads();
   }
-  store_tile(P, nr, I0, J0, bi != bj, accumulate, accR, accI, wr, wc, lane);
+  if (SCALED) unscale(esorted[(nch - 1) % nv]);
+  if (accumulate || nfold > 0) add_tile(P, nr, I0, J0, bi != bj, accR, accI, wr, wc, lane);
+  else store_tile(P, nr, I0, J0, bi != bj, 0, accR, accI, wr, wc, lane);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -577,15 +693,36 @@ __global__ void band_exponent_kernel(const float *__restrict__ vmax, int nv, con
   band_exp[v] = max(-60, min(60, e));
 }
 
+// Bands ordered by exponent (a stable counting sort over the clamped range [-60, 60], one thread):
+// order[k] is the k-th band, es[k] its exponent.
+__global__ void band_order_kernel(const int *__restrict__ band_exp, int nv, int *__restrict__ order,
+                                  int *__restrict__ es) {
+  __shared__ int start[122];
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < 122; ++i) start[i] = 0;
+  for (int v = 0; v < nv; ++v) start[band_exp[v] + 61]++;
+  for (int i = 1; i < 122; ++i) start[i] += start[i - 1];     // start[e + 60] = first slot of exponent e
+  for (int v = 0; v < nv; ++v) {
+    const int e = band_exp[v];
+    const int k = start[e + 60]++;
+    order[k] = v;
+    es[k] = e;
+  }
+}
+
+size_t band_exp_ints(int nv, int nc) { return (size_t)4 * nv + nc; }
+
 hipError_t launch_band_exponents(const float2 *psi_v, int nv, const float2 *psi_c, int nc, int nr,
                                  const float *scale, int ldsc, int *band_exp, hipStream_t s) {
-  // band_exp is followed in the same workspace by nv + nc floats of row maxima.
-  float *vmax = reinterpret_cast<float *>(band_exp + nv);
+  // layout (band_exp_ints): exponents [nv], band order [nv], sorted exponents [nv], then the row
+  // maxima as floats: occupied [nv], unoccupied [nc]
+  float *vmax = reinterpret_cast<float *>(band_exp + 3 * nv);
   float *cmax = vmax + nv;
   hipLaunchKernelGGL(absmax_rows_kernel, dim3(nv), dim3(256), 0, s, psi_v, nv, nr, vmax);
   hipLaunchKernelGGL(absmax_rows_kernel, dim3(nc), dim3(256), 0, s, psi_c, nc, nr, cmax);
   hipLaunchKernelGGL(band_exponent_kernel, dim3((nv + 63) / 64), dim3(64), 0, s, vmax, nv, cmax, nc, scale, ldsc,
                      band_exp);
+  hipLaunchKernelGGL(band_order_kernel, dim3(1), dim3(64), 0, s, band_exp, nv, band_exp + nv, band_exp + 2 * nv);
   return hipGetLastError();
 }
 
@@ -604,6 +741,7 @@ static const TileCfg kTiles[] = {
   {"bf16split_t128_ws_k32", GW_SPLIT_BF16},
   {"bf16split_t128_ws_prio", GW_SPLIT_BF16},
   {"bf16split_t128_ws_k32_prio", GW_SPLIT_BF16},
+  {"fp16split_t128_ws_k32_scaled", GW_SPLIT_FP16_SCALED},
 };
 
 int herk_tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -616,7 +754,7 @@ int herk_default_tile(int precision, int nr) {
   switch (precision) {
     case GW_FP32: return 4;
     case GW_SPLIT_BF16: return 7;
-    case GW_SPLIT_FP16_SCALED: return 3;
+    case GW_SPLIT_FP16_SCALED: return 10;
   }
   return -1;
 }
@@ -639,13 +777,17 @@ hipError_t launch_herk(int precision, int tile, const float2 *psi_v, const float
     case 4: GW_LAUNCH((herk_fp32_kernel<true, true>), psi_v, psi_c, scale, ldsc, p, nr, nv, nc, ntiles, accumulate); break;
     case 5: GW_LAUNCH((herk_split_kernel<__bf16, false, true>), psi_v, psi_c, scale, ldsc, band_exp, p, nr, nv, nc, ntiles,
                       accumulate); break;
-#define GW_WS(KW_, PRIO_)                                                                                        \
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_ws_kernel<KW_, PRIO_>), grid, dim3(2 * NTHR), 0, s, psi_v, psi_c, \
-                     scale, ldsc, p, nr, nv, nc, ntiles, accumulate)
-    case 6: GW_WS(16, false); break;
-    case 7: GW_WS(32, false); break;
-    case 8: GW_WS(16, true); break;
-    case 9: GW_WS(32, true); break;
+#define GW_WS(T_, KW_, PRIO_, SC_)                                                                            \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_ws_kernel<T_, KW_, PRIO_, SC_>), grid, dim3(2 * NTHR), 0, s, psi_v, \
+                     psi_c, scale, ldsc, band_exp, p, nr, nv, nc, ntiles, accumulate)
+    case 6: GW_WS(__bf16, 16, false, false); break;
+    case 7: GW_WS(__bf16, 32, false, false); break;
+    case 8: GW_WS(__bf16, 16, true, false); break;
+    case 9: GW_WS(__bf16, 32, true, false); break;
+    case 10:
+      if (!band_exp) return hipErrorInvalidValue;
+      GW_WS(_Float16, 32, false, true);
+      break;
 #undef GW_WS
     default:
       return hipErrorInvalidValue;

@@ -41,7 +41,7 @@ def setup():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 1e-4)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 1e-4), ("fp16", 1e-4)])
 def test_production_size(setup, prec, tol):
     gw, s, prr = setup["gw"], setup["s"], setup["prr"]
     print(f"[case] 36^3 build, {prec}", flush=True)

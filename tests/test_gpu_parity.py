@@ -240,3 +240,56 @@ def test_every_tile(gw, tile, name, n, nv, nc, r2):
     e = orc.rel_f(p.cpu().numpy(), ref)
     print(f"tile {name}: rel_F(P) = {e:.3e}")
     assert e < tol
+
+
+def test_fp16_scaled_tiles_agree_with_wide_band_exponents(gw):
+    """Occupied energies spread over 400 eV give per-band exponents several units apart, so the
+    wave-specialised FP16 tile rescales its accumulators between bands; it must agree with the
+    per-band-fold tile and with the oracle."""
+    s = sys_c64(12, 8, 64, 10.0, seed=5)
+    e_v = np.linspace(-400.0, -0.5, 8) / 27.211386245988
+    names = gw.tile_names()
+    t_old, t_ws = names.index("fp16split_t128_scaled_vouter"), names.index("fp16split_t128_ws_k32_scaled")
+    pv, pc = c64(s.psi_v), c64(s.psi_c)
+    a = gw.polarizability_r(pv, pc, e_v, s.e_c, precision="fp16", tile=t_old).cpu().numpy()
+    b = gw.polarizability_r(pv, pc, e_v, s.e_c, precision="fp16", tile=t_ws).cpu().numpy()
+    ref = orc.polarizability_r(s.psi_v, s.psi_c, e_v, s.e_c)
+    ea, eb, eab = orc.rel_f(a, ref), orc.rel_f(b, ref), orc.rel_f(b, a)
+    print(f"fp16 per-band fold {ea:.2e}, wave-specialised with rescaling {eb:.2e}, between them {eab:.2e}")
+    # an FP16 hi + lo pair carries 22 bits: the wave-specialised tile reaches that level; the older
+    # single-role tile stays within the split-precision bound
+    assert eb < 1e-6 and ea < 1e-4 and eab < 1e-4
+
+
+@pytest.mark.parametrize("prec,tile_name,tol", [("bf16", "bf16split_t128_ws_k32", 1e-4),
+                                                ("bf16", "bf16split_t128_ws", 1e-4),
+                                                ("fp16", "fp16split_t128_ws_k32_scaled", 2e-5)])
+@pytest.mark.parametrize("nv,nc", [(32, 1024), (64, 600), (64, 1024)])
+def test_split_two_level_sum(gw, prec, tile_name, tol, nv, nc):
+    """K = nv*nc of 32768 (no fold), 38400 (one fold, ragged) and 65536 (a fold between two full blocks)
+    on an 8^3 grid with random (non-orthogonal) orbitals: the wave-specialised kernels add their
+    partial sums into P every 32768 pairs.  Also accumulating onto an existing P, and the written
+    mirror half."""
+    rng = np.random.default_rng(nv * nc)
+    nr = 512
+    pv = ((rng.standard_normal((nv, nr)) + 1j * rng.standard_normal((nv, nr))) / np.sqrt(2 * nr)).astype(np.complex64)
+    pc = ((rng.standard_normal((nc, nr)) + 1j * rng.standard_normal((nc, nr))) / np.sqrt(2 * nr)).astype(np.complex64)
+    e_v, e_c = gs.energies(rng, nv, nc)
+    tile = gw.tile_names().index(tile_name)
+    print(f"[case] {tile_name} nv={nv} nc={nc} K={nv * nc}", flush=True)
+    p = gw.polarizability_r(c64(pv), c64(pc), e_v, e_c, precision=prec, tile=tile)
+    torch.cuda.synchronize()
+    ref = orc.polarizability_r(pv, pc, e_v, e_c)
+    got = p.cpu().numpy()
+    e = orc.rel_f(got, ref)
+    herm = np.max(np.abs(got - got.conj().T)) / np.max(np.abs(got))
+    print(f"rel_F(P) = {e:.2e}, |P - P^H| / max|P| = {herm:.1e}")
+    assert e < tol and herm < 0.1 * tol
+    # accumulate: P holds the first half of the occupied bands, the call adds the second half
+    h = nv // 2
+    gw.polarizability_r(c64(pv[:h]), c64(pc), e_v[:h], e_c, precision=prec, tile=tile, out=p)
+    gw.polarizability_r(c64(pv[h:]), c64(pc), e_v[h:], e_c, precision=prec, tile=tile, accumulate=True, out=p)
+    torch.cuda.synchronize()
+    e2 = orc.rel_f(p.cpu().numpy(), ref)
+    print(f"accumulated in two calls: rel_F(P) = {e2:.2e}")
+    assert e2 < tol
