@@ -83,12 +83,11 @@ __device__ __forceinline__ void store_tile(float2 *__restrict__ P, int nr, int I
       }
 }
 
-// Partial-sum store of the two-level sum: adds -acc to the tile and conj(-acc) to its mirror
-// (off-diagonal tiles) with atomic adds that return nothing, so no old values are loaded into
-// registers.  Every element has exactly one writer, so the result does not depend on timing.
-__device__ __forceinline__ void add_tile(float2 *__restrict__ P, int nr, int I0, int J0, bool mirror,
-                                         const f32x16 (&re)[2][2], const f32x16 (&im)[2][2], int wr, int wc,
-                                         int lane) {
+// Final store after partial sums were folded into the tile: P += -acc on the tile itself, then the
+// mirror (off-diagonal tiles) is written as the conjugate of the new value.
+__device__ __forceinline__ void store_tile_after_folds(float2 *__restrict__ P, int nr, int I0, int J0, bool mirror,
+                                                       const f32x16 (&re)[2][2], const f32x16 (&im)[2][2], int wr,
+                                                       int wc, int lane) {
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -100,14 +99,11 @@ __device__ __forceinline__ void add_tile(float2 *__restrict__ P, int nr, int I0,
         const int row = I0 + wr * 64 + rb * 32 + i;
         const int col = J0 + wc * 64 + cb * 32 + j;
         if (row < nr && col < nr) {
-          float *d = reinterpret_cast<float *>(P + (size_t)row * nr + col);
-          __hip_atomic_fetch_add(d, -re[rb][cb][e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_fetch_add(d + 1, -im[rb][cb][e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (mirror) {
-            float *m = reinterpret_cast<float *>(P + (size_t)col * nr + row);
-            __hip_atomic_fetch_add(m, -re[rb][cb][e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(m + 1, im[rb][cb][e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
+          float2 *d = P + (size_t)row * nr + col;
+          const float2 o = *d;
+          const float2 v = make_float2(o.x - re[rb][cb][e], o.y - im[rb][cb][e]);
+          *d = v;
+          if (mirror) P[(size_t)col * nr + row] = make_float2(v.x, -v.y);
         }
       }
 }
@@ -453,9 +449,9 @@ template <> struct NarrowSplit<_Float16> {
 };
 
 // Two-level sum: every FOLD_PAIRS pairs of K the consumers add their partial sums into the tile of
-// P and its mirror and restart from zero, so FP32 rounding in the accumulators grows with the block
-// length instead of with K.  The first block is stored (unless accumulating into P), later blocks
-// are added.
+// P (read-modify-write of the tile only; with accumulate set, of its mirror too) and restart from
+// zero, so FP32 rounding in the accumulators grows with the block length instead of with K.  Without
+// accumulate, the final store writes the mirror as the conjugate of the finished tile.
 constexpr int FOLD_PAIRS = 32768;
 
 // SCALED (FP16): band v's pair products carry 2^{e_v}, so its products carry 2^{2 e_v}.  The bands
@@ -641,8 +637,8 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
       // all of them live across the loop and spills
       int lane_f = lane;
       asm volatile("" : "+v"(lane_f));
-      if (accumulate || nfold > 0) add_tile(P, nr, I0, J0, bi != bj, accR, accI, wr, wc, lane_f);
-      else store_tile(P, nr, I0, J0, bi != bj, 0, accR, accI, wr, wc, lane_f);
+      // the tile only (its mirror is written once at the end), unless accumulating into P
+      store_tile(P, nr, I0, J0, accumulate && bi != bj, accumulate || nfold > 0, accR, accI, wr, wc, lane_f);
       ++nfold;
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -654,8 +650,8 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
     __syncthreads();
   }
   if (SCALED) unscale(esorted[(nch - 1) % nv]);
-  if (accumulate || nfold > 0) add_tile(P, nr, I0, J0, bi != bj, accR, accI, wr, wc, lane);
-  else store_tile(P, nr, I0, J0, bi != bj, 0, accR, accI, wr, wc, lane);
+  if (nfold == 0 || accumulate) store_tile(P, nr, I0, J0, bi != bj, accumulate || nfold > 0, accR, accI, wr, wc, lane);
+  else store_tile_after_folds(P, nr, I0, J0, bi != bj, accR, accI, wr, wc, lane);
 }
 
 // ---------------------------------------------------------------------------------------------
