@@ -228,7 +228,9 @@ def _tiles():
         return [(i, f"tile{i}") for i in range(6)]
 
 
-@pytest.mark.parametrize("n,nv,nc,r2", [(12, 8, 64, 10.0), (10, 3, 37, 6.0)])
+@pytest.mark.parametrize("n,nv,nc,r2", [(12, 8, 64, 10.0), (10, 3, 37, 6.0),
+                                        (4, 1, 1, 1.0),       # one pair, one partial tile
+                                        (6, 1, 40, 6.0)])     # one occupied band over several chunks
 @pytest.mark.parametrize("tile,name", _tiles())
 def test_every_tile(gw, tile, name, n, nv, nc, r2):
     prec = "fp32" if name.startswith("fp32") else ("bf16" if name.startswith("bf16") else "fp16")
