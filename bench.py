@@ -111,7 +111,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="si36", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"], help="headline precision")
-    ap.add_argument("--compare", default="fp32", help="comma list of other precisions to time ('' for none)")
+    ap.add_argument("--compare", default="fp32,fp16", help="comma list of other precisions to time ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--tile", type=int, default=-1)
@@ -309,6 +309,27 @@ def main():
                  "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s"}
         log(f"static exchange (16 bands): {t * 1e3:.1f} ms")
 
+    # learned band tail at N_g: features of the truncated P~, the MLP forward pass and the correction
+    # (seeded initial weights: the cost does not depend on training)
+    tail_m = None
+    if args.workload == "si36":
+        from paper_1810_07772_amd import tail as gw_tail
+        feat = gw.tail_features(pgg, s.n, s.a_bohr, s.q, s.miller, nc, float(s.e_c[-1]))
+        model = gw.TailModel(gs.mlp_init(0), gw_tail.fit_norm([feat]))
+        model.correct(pgg, feat)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        feat = gw.tail_features(pgg, s.n, s.a_bohr, s.q, s.miller, nc, float(s.e_c[-1]), out=feat)
+        corr, fb = model.correct(pgg, feat)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3
+        tail_m = {"ms": round(t * 1e3, 3), "ng": ng, "fallback": fb,
+                  "mlp_flop": 2.0 * ng * (4 * 128 + 128 * 128 + 128 * 33),
+                  "note": "features + forward + diag(d) + U U^H correction of an N_g x N_g P~"}
+        log(f"learned tail: {t * 1e3:.2f} ms for N_g = {ng}")
+        del model, corr
+
     # eight q-points on the 32^3 grid (Nv 96, Nc 768 each) through one captured graph: the first call
     # tunes and captures, the second (timed) replays it
     batched = None
@@ -395,6 +416,7 @@ def main():
         "eps_inverse_cholesky_roofline": chol,
         "eps_inverse_newton": newton,
         "batched_q": batched,
+        "learned_tail": tail_m,
         "plasmon_pole": ppole,
         "sigma_static": sigma,
     }
