@@ -395,7 +395,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"bf16": "bf16x3-split/fp32-acc", "fp16": "fp16x3-split-scaled/fp32-acc",
                   "fp32": "fp32"}[args.precision],
-        "data": "synthetic (seeded random plane-wave orbitals, QR-orthonormalised; see DESIGN.md)",
+        "data": "synthetic: seeded random plane-wave orbitals (Gaussian envelope, QR-orthonormalised), random band energies",
         "config": {"workload": f"{args.workload}: {wl['n']}^3 grid (N_r={nr}), Nv={nv}, Nc={nc}, K={K}, "
                                f"N_g={ng}, q=0, P(r,r') complex64 {nr * nr * 8 / 1e9:.1f} GB",
                    "precision": args.precision, "tile": args.tile},

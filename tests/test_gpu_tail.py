@@ -125,7 +125,7 @@ def test_features_target_and_correction(gw):
 @pytest.mark.timeout(900)
 def test_training_and_gain_on_larger_systems(gw):
     """Train on 200 seeded 16^3 systems (Nc in {64, 96, 128}, each against 4 Nc; 180 train, 20 validation),
-    then correct the 24^3 systems (Nv 32) truncated at Nc = 256 and judge them against the plain Nc = 1024 sum."""
+    then correct the 24^3 systems (Nv 32) truncated at Nc = 256 and compare them with the plain Nc = 1024 sum."""
     from paper_1810_07772_amd import tail
     entries = []
     for k in range(200):
