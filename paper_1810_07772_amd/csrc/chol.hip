@@ -195,43 +195,66 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
     a[i][j] = v;
   }
   __syncthreads();
-  // unblocked right-looking Cholesky on the lower triangle
+  // unblocked right-looking Cholesky on the lower triangle, with unscaled columns: step j subtracts
+  // s_j s_j^H / d_j (d_j the pivot) from the trailing lower triangle, which needs one barrier per
+  // step; column j is final after step j and is scaled to L in one pass at the end.
   for (int j = 0; j < NB; ++j) {
-    if (tid == 0) {
-      double d = a[j][j].x;
-      if (!(d > 0.0) || !isfinite(d)) {
-        if (j < nb && bad == 0) bad = k0 + j + 1;
-        d = 1.0;
-      }
-      a[j][j] = make_double2(sqrt(d), 0.0);
+    __syncthreads();
+    double d = a[j][j].x;
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (tid == 0 && j < nb && bad == 0) bad = k0 + j + 1;
+      d = 1.0;
     }
-    __syncthreads();
-    const double ljj = a[j][j].x;
-    for (int i = j + 1 + tid; i < NB; i += 256) { a[i][j].x /= ljj; a[i][j].y /= ljj; }
-    __syncthreads();
-    // trailing update a[i][m] -= a[i][j] conj(a[m][j]) for j < m <= i
+    const double dinv = 1.0 / d;
     for (int idx = tid; idx < NB * NB; idx += 256) {
       const int i = idx / NB, m = idx % NB;
       if (m > j && m <= i) {
         const double2 p = a[i][j], q = a[m][j];
-        a[i][m].x -= p.x * q.x + p.y * q.y;
-        a[i][m].y -= p.y * q.x - p.x * q.y;
+        a[i][m].x -= (p.x * q.x + p.y * q.y) * dinv;
+        a[i][m].y -= (p.y * q.x - p.x * q.y) * dinv;
       }
     }
-    __syncthreads();
   }
-  // inverse of the lower-triangular factor, one column per thread: L x = e_col
-  if (tid < NB) {
-    const int col = tid;
+  __syncthreads();
+  // L = column j over sqrt(d_j) (bad pivots were replaced by 1 and flagged)
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int i = idx / NB, j = idx % NB;
+    if (j <= i) {
+      double d = a[j][j].x;
+      if (!(d > 0.0) || !isfinite(d)) d = 1.0;
+      const double r = sqrt(d);
+      x[i][j] = (i == j) ? make_double2(r, 0.0) : make_double2(a[i][j].x / r, a[i][j].y / r);
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int i = idx / NB, j = idx % NB;
+    if (j <= i) a[i][j] = x[i][j];
+  }
+  __syncthreads();
+  // inverse of the lower-triangular factor by forward substitution on each unit vector, L x = e_col:
+  // eight lanes per column split the dot product over m and reduce it with shuffles; a column's eight
+  // lanes sit in one wave, so the rows of one column need no workgroup barrier between them
+  {
+    const int col = tid >> 3, part = tid & 7;
     for (int i = 0; i < NB; ++i) {
-      double2 s = make_double2(i == col ? 1.0 : 0.0, 0.0);
-      for (int m = col; m < i; ++m) {
+      double sr = 0.0, si = 0.0;
+      for (int m = col + part; m < i; m += 8) {
         const double2 l = a[i][m], v = x[m][col];
-        s.x -= l.x * v.x - l.y * v.y;
-        s.y -= l.x * v.y + l.y * v.x;
+        sr += l.x * v.x - l.y * v.y;
+        si += l.x * v.y + l.y * v.x;
       }
-      const double d = a[i][i].x;
-      x[i][col] = (i < col) ? make_double2(0.0, 0.0) : make_double2(s.x / d, s.y / d);
+      for (int off = 4; off > 0; off >>= 1) {
+        sr += __shfl_xor(sr, off, 8);
+        si += __shfl_xor(si, off, 8);
+      }
+      if (part == 0) {
+        const double d = a[i][i].x;
+        const double er = (i == col ? 1.0 : 0.0) - sr;
+        x[i][col] = (i < col) ? make_double2(0.0, 0.0) : make_double2(er / d, -si / d);
+      }
+      __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this wave's LDS write lands before the next row reads it
+      __builtin_amdgcn_wave_barrier();
     }
   }
   __syncthreads();
