@@ -91,3 +91,23 @@ def test_production_size(setup, prec, tol):
         es = orc.rel_f(ss.cpu().numpy(), so.sigma_sex(ft, pp.screening_part(e, sv)))
         print(f"static exchange, 16 bands x 128 occupied: sigma_x rel_F {ex:.1e}, sigma_sex rel_F {es:.1e}")
         assert ex < 1e-6 and es < 1e-6
+
+
+@pytest.mark.timeout(300)
+def test_pair_products_production_block(setup):
+    """The standalone pair products in the benchmark's launch: 8 occupied x 1024 unoccupied bands over
+    all 46656 points (3.06 GB written); sampled pair rows against the oracle's Eq.(fdef)."""
+    gw, s = setup["gw"], setup["s"]
+    nvb = 8
+    f = gw.pair_products(setup["pv"][:nvb].contiguous(), setup["pc"], s.e_v[:nvb], s.e_c)
+    torch.cuda.synchronize()
+    rows = np.array([0, 1, 1023, 1024, 4 * 1024 + 517, 8 * 1024 - 1])        # (v, c) = (0,0) ... (7,1023)
+    got = f[torch.from_numpy(rows).to(f.device)].cpu().numpy()
+    pv = setup["pv"][:nvb].cpu().numpy()
+    pc = setup["pc"].cpu().numpy()
+    v, c = rows // 1024, rows % 1024
+    ref = orc.pair_products(pv[np.unique(v)], pc, s.e_v[np.unique(v)], s.e_c)
+    ref = ref.reshape(len(np.unique(v)), 1024, -1)[np.searchsorted(np.unique(v), v), c]
+    e = orc.rel_f(got, ref)
+    print(f"pair products at 36^3: sampled rows rel_F {e:.2e}")
+    assert e < 1e-6
