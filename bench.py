@@ -69,7 +69,7 @@ def parity_small(gw, torch, prec):
 
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "herk_bf16split_si36_pmc.md")
-PMC_KERNEL = {"bf16split_t128_ws_k32": "herk_split_ws_kernel<__bf16, 32, false, false>"}
+PMC_KERNEL = {"bf16split_t128_ws2_k32": "herk_split_ws_kernel<__bf16, 32, false, false, 2>"}
 
 
 def measured_traffic(tile_name, workload):

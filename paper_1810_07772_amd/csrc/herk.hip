@@ -412,12 +412,16 @@ __global__ __launch_bounds__(NTHR, 1) void herk_split_kernel(const float2 *__res
 }
 
 // ---------------------------------------------------------------------------------------------
-// Wave-specialised split kernel: 8 waves per workgroup.  Waves 0-3 only issue MFMAs (each owns a
-// 64x64 quadrant of the 128x128 tile); waves 4-7 only form pair products, split them and stage
-// them in LDS for the next stage.  Each SIMD then holds one MFMA wave and one producer wave, so
-// the producer's VALU work runs while the matrix core executes the other wave's MFMAs.  K order:
-// unoccupied chunk outer, occupied band inner (the psi_c chunk of a producer thread stays in
-// registers for nv stages).  Loads are branch-free: indices are clamped and the value masked.
+// Wave-specialised split kernel: 4 + 4 NPW waves per workgroup.  Waves 0-3 only issue MFMAs (each
+// owns a 64x64 quadrant of the 128x128 tile); the other waves only form pair products, split them
+// and stage them in LDS for the next stage.  Each SIMD then holds one MFMA wave and NPW producer
+// waves, so the producers' VALU work runs while the matrix core executes the other wave's MFMAs.
+// One wave issues a VALU instruction only every 8 or so cycles, and beside a busy matrix core one
+// producer wave per SIMD does not keep up with the MFMAs; with NPW = 2 each producer takes half of
+// the stage's pairs and the consumers fit their operands into the 168 registers that three waves
+// per SIMD leave.  K order: unoccupied chunk outer, occupied band inner (the psi_c chunk of a
+// producer thread stays in registers for nv stages).  Loads are branch-free: indices are clamped
+// and the value masked.
 // ---------------------------------------------------------------------------------------------
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -459,8 +463,8 @@ constexpr int FOLD_PAIRS = 32768;
 // are multiplied by the exact power of two 2^{2(e_new - e_old)} whenever the exponent changes
 // between stages (a few times per unoccupied chunk), and by 2^{-2 e_last} at the end: the same
 // per-band scale as a fold per band, without a second accumulator set.
-template <typename T, int KW, bool PRIO, bool SCALED>
-__global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2 *__restrict__ psi_v,
+template <typename T, int KW, bool PRIO, bool SCALED, int NPW>
+__global__ __launch_bounds__((1 + NPW) * NTHR, 1) void herk_split_ws_kernel(const float2 *__restrict__ psi_v,
                                                                      const float2 *__restrict__ psi_c,
                                                                      const float *__restrict__ scale, int ldsc,
                                                                      const int *__restrict__ band_exp,
@@ -484,21 +488,24 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
   const int nch = nv * nchc;
   const bool producer = wave >= 4;
 
-  // ---- producer state: one grid point of the rows (waves 4, 6) or columns (waves 5, 7)
+  // ---- producer state: one grid point of the rows (even pw) or columns (odd pw), and KP of the
+  // stage's KW pairs starting at koff (NPW producer waves share a SIMD, each taking KW / NPW pairs)
+  constexpr int KP = KW / NPW;
   const int pw = wave - 4;
   const int pside = pw & 1;
-  const int ppt = lane + 64 * (pw >> 1);
+  const int ppt = lane + 64 * ((pw >> 1) & 1);
+  const int koff = (pw >> 2) * KP;
   // Loads need no masks: the scale table is zero for unoccupied bands past nc (so those pair
   // products vanish), and a point past nr only feeds output entries that are never stored, so
   // out-of-range indices are clamped to valid addresses.
   const int gpt = min((pside ? J0 : I0) + ppt, nr - 1);
-  float2 pc[KW], pcn[KW];
+  float2 pc[KP], pcn[KP];
   float2 pvv;
-  float sc[KW];
+  float sc[KP];
 
-  auto load_c = [&](float2 (&dst)[KW], int cc) {   // psi_c of chunk cc at this thread's point
+  auto load_c = [&](float2 (&dst)[KP], int cc) {   // psi_c of chunk cc at this thread's point
 #pragma unroll
-    for (int k = 0; k < KW; ++k) dst[k] = psi_c[(size_t)min(cc * KW + k, nc - 1) * nr + gpt];
+    for (int k = 0; k < KP; ++k) dst[k] = psi_c[(size_t)min(cc * KW + koff + k, nc - 1) * nr + gpt];
   };
   auto load_v = [&](int ch) {                       // psi_v and the scales of stage ch
     const int vi = ch % nv, c0 = (ch / nv) * KW;
@@ -509,15 +516,15 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
       pvv.x *= m;
       pvv.y *= m;
     }
-    const float *srow = scale + (size_t)v * ldsc + c0;
+    const float *srow = scale + (size_t)v * ldsc + c0 + koff;
 #pragma unroll
-    for (int k = 0; k < KW; ++k) sc[k] = srow[k];
+    for (int k = 0; k < KP; ++k) sc[k] = srow[k];
   };
   auto produce = [&](int buf) {
-    u32x4 *dh = reinterpret_cast<u32x4 *>(pside ? &sBh[buf][ppt][0] : &sAh[buf][ppt][0]);
-    u32x4 *dl = reinterpret_cast<u32x4 *>(pside ? &sBl[buf][ppt][0] : &sAl[buf][ppt][0]);
+    u32x4 *dh = reinterpret_cast<u32x4 *>(pside ? &sBh[buf][ppt][2 * koff] : &sAh[buf][ppt][2 * koff]);
+    u32x4 *dl = reinterpret_cast<u32x4 *>(pside ? &sBl[buf][ppt][2 * koff] : &sAl[buf][ppt][2 * koff]);
 #pragma unroll
-    for (int g = 0; g < KW / 4; ++g) {
+    for (int g = 0; g < KP / 4; ++g) {
       u32x4 hv, lv;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
@@ -548,7 +555,7 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
       if (ch + 1 < nch) {
         if ((ch + 1) % nv == 0) {                          // stage ch+1 opens the next unoccupied chunk
 #pragma unroll
-          for (int k = 0; k < KW; ++k) pc[k] = pcn[k];
+          for (int k = 0; k < KP; ++k) pc[k] = pcn[k];
         }
         produce((ch & 1) ^ 1);
         if (ch + 2 < nch) {
@@ -606,16 +613,17 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
 #pragma unroll
     for (int g = 0; g < KW / 8; ++g) {
       const int ko = g * 16 + kq * 8;
-      const vec ah0 = *reinterpret_cast<const vec *>(&sAh[buf][ar0][ko]);
-      const vec ah1 = *reinterpret_cast<const vec *>(&sAh[buf][ar0 + 32][ko]);
-      const vec al0 = *reinterpret_cast<const vec *>(&sAl[buf][ar0][ko]);
-      const vec al1 = *reinterpret_cast<const vec *>(&sAl[buf][ar0 + 32][ko]);
-      const vec bh0 = *reinterpret_cast<const vec *>(&sBh[buf][bc0][ko]);
-      const vec bh1 = *reinterpret_cast<const vec *>(&sBh[buf][bc0 + 32][ko]);
-      const vec bl0 = *reinterpret_cast<const vec *>(&sBl[buf][bc0][ko]);
-      const vec bl1 = *reinterpret_cast<const vec *>(&sBl[buf][bc0 + 32][ko]);
-      const vec yh0 = rot_neg(bh0), yh1 = rot_neg(bh1), yl0 = rot_neg(bl0), yl1 = rot_neg(bl1);
-      // eight independent accumulators per product, so consecutive MFMAs never chain
+      if (NPW == 1) {
+        const vec ah0 = *reinterpret_cast<const vec *>(&sAh[buf][ar0][ko]);
+        const vec ah1 = *reinterpret_cast<const vec *>(&sAh[buf][ar0 + 32][ko]);
+        const vec al0 = *reinterpret_cast<const vec *>(&sAl[buf][ar0][ko]);
+        const vec al1 = *reinterpret_cast<const vec *>(&sAl[buf][ar0 + 32][ko]);
+        const vec bh0 = *reinterpret_cast<const vec *>(&sBh[buf][bc0][ko]);
+        const vec bh1 = *reinterpret_cast<const vec *>(&sBh[buf][bc0 + 32][ko]);
+        const vec bl0 = *reinterpret_cast<const vec *>(&sBl[buf][bc0][ko]);
+        const vec bl1 = *reinterpret_cast<const vec *>(&sBl[buf][bc0 + 32][ko]);
+        const vec yh0 = rot_neg(bh0), yh1 = rot_neg(bh1), yl0 = rot_neg(bl0), yl1 = rot_neg(bl1);
+        // eight independent accumulators per product, so consecutive MFMAs never chain
 #define GW_PROD8(A0, A1, B0, B1, Y0, Y1)                          \
   accR[0][0] = SplitTraits<T>::mfma(A0, B0, accR[0][0]);           \
   accI[0][0] = SplitTraits<T>::mfma(A0, Y0, accI[0][0]);           \
@@ -625,10 +633,41 @@ __global__ __launch_bounds__(2 * NTHR, 1) void herk_split_ws_kernel(const float2
   accI[1][0] = SplitTraits<T>::mfma(A1, Y0, accI[1][0]);           \
   accR[1][1] = SplitTraits<T>::mfma(A1, B1, accR[1][1]);           \
   accI[1][1] = SplitTraits<T>::mfma(A1, Y1, accI[1][1]);
-      GW_PROD8(ah0, ah1, bh0, bh1, yh0, yh1)     // hi * hi
-      GW_PROD8(ah0, ah1, bl0, bl1, yl0, yl1)     // hi * lo
-      GW_PROD8(al0, al1, bh0, bh1, yh0, yh1)     // lo * hi
+        GW_PROD8(ah0, ah1, bh0, bh1, yh0, yh1)     // hi * hi
+        GW_PROD8(ah0, ah1, bl0, bl1, yl0, yl1)     // hi * lo
+        GW_PROD8(al0, al1, bh0, bh1, yh0, yh1)     // lo * hi
 #undef GW_PROD8
+      } else {
+        // three waves share the SIMD, so at most 168 registers: the products run in an order
+        // that keeps three operand pairs live (real parts, then the rotated B in place for the
+        // imaginary parts, and B's lo half last)
+#define GW_PROD4(ACC, A0, A1, B0, B1)                        \
+  ACC[0][0] = SplitTraits<T>::mfma(A0, B0, ACC[0][0]);        \
+  ACC[0][1] = SplitTraits<T>::mfma(A0, B1, ACC[0][1]);        \
+  ACC[1][0] = SplitTraits<T>::mfma(A1, B0, ACC[1][0]);        \
+  ACC[1][1] = SplitTraits<T>::mfma(A1, B1, ACC[1][1]);
+        const vec ah0 = *reinterpret_cast<const vec *>(&sAh[buf][ar0][ko]);
+        const vec ah1 = *reinterpret_cast<const vec *>(&sAh[buf][ar0 + 32][ko]);
+        vec b0 = *reinterpret_cast<const vec *>(&sBh[buf][bc0][ko]);
+        vec b1 = *reinterpret_cast<const vec *>(&sBh[buf][bc0 + 32][ko]);
+        GW_PROD4(accR, ah0, ah1, b0, b1)           // hi * hi
+        {
+          const vec al0 = *reinterpret_cast<const vec *>(&sAl[buf][ar0][ko]);
+          const vec al1 = *reinterpret_cast<const vec *>(&sAl[buf][ar0 + 32][ko]);
+          GW_PROD4(accR, al0, al1, b0, b1)         // lo * hi
+          b0 = rot_neg(b0);
+          b1 = rot_neg(b1);
+          GW_PROD4(accI, ah0, ah1, b0, b1)
+          GW_PROD4(accI, al0, al1, b0, b1)
+        }
+        b0 = *reinterpret_cast<const vec *>(&sBl[buf][bc0][ko]);
+        b1 = *reinterpret_cast<const vec *>(&sBl[buf][bc0 + 32][ko]);
+        GW_PROD4(accR, ah0, ah1, b0, b1)           // hi * lo
+        b0 = rot_neg(b0);
+        b1 = rot_neg(b1);
+        GW_PROD4(accI, ah0, ah1, b0, b1)
+#undef GW_PROD4
+      }
     }
     if ((ch + 1) % FOLD_STAGES == 0 && ch + 1 < nch) {
       // two-level sum: this block's partial goes into the tile, the accumulators restart from zero
@@ -738,6 +777,8 @@ static const TileCfg kTiles[] = {
   {"bf16split_t128_ws_prio", GW_SPLIT_BF16},
   {"bf16split_t128_ws_k32_prio", GW_SPLIT_BF16},
   {"fp16split_t128_ws_k32_scaled", GW_SPLIT_FP16_SCALED},
+  {"bf16split_t128_ws2_k32", GW_SPLIT_BF16},
+  {"fp16split_t128_ws2_k32_scaled", GW_SPLIT_FP16_SCALED},
 };
 
 int herk_tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -749,8 +790,8 @@ int herk_default_tile(int precision, int nr) {
   (void)nr;
   switch (precision) {
     case GW_FP32: return 4;
-    case GW_SPLIT_BF16: return 7;
-    case GW_SPLIT_FP16_SCALED: return 10;
+    case GW_SPLIT_BF16: return 11;
+    case GW_SPLIT_FP16_SCALED: return 12;
   }
   return -1;
 }
@@ -773,16 +814,21 @@ hipError_t launch_herk(int precision, int tile, const float2 *psi_v, const float
     case 4: GW_LAUNCH((herk_fp32_kernel<true, true>), psi_v, psi_c, scale, ldsc, p, nr, nv, nc, ntiles, accumulate); break;
     case 5: GW_LAUNCH((herk_split_kernel<__bf16, false, true>), psi_v, psi_c, scale, ldsc, band_exp, p, nr, nv, nc, ntiles,
                       accumulate); break;
-#define GW_WS(T_, KW_, PRIO_, SC_)                                                                            \
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_ws_kernel<T_, KW_, PRIO_, SC_>), grid, dim3(2 * NTHR), 0, s, psi_v, \
-                     psi_c, scale, ldsc, band_exp, p, nr, nv, nc, ntiles, accumulate)
-    case 6: GW_WS(__bf16, 16, false, false); break;
-    case 7: GW_WS(__bf16, 32, false, false); break;
-    case 8: GW_WS(__bf16, 16, true, false); break;
-    case 9: GW_WS(__bf16, 32, true, false); break;
+#define GW_WS(T_, KW_, PRIO_, SC_, NPW_)                                                                  \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_ws_kernel<T_, KW_, PRIO_, SC_, NPW_>), grid, dim3((1 + NPW_) * NTHR), \
+                     0, s, psi_v, psi_c, scale, ldsc, band_exp, p, nr, nv, nc, ntiles, accumulate)
+    case 6: GW_WS(__bf16, 16, false, false, 1); break;
+    case 7: GW_WS(__bf16, 32, false, false, 1); break;
+    case 8: GW_WS(__bf16, 16, true, false, 1); break;
+    case 9: GW_WS(__bf16, 32, true, false, 1); break;
     case 10:
       if (!band_exp) return hipErrorInvalidValue;
-      GW_WS(_Float16, 32, false, true);
+      GW_WS(_Float16, 32, false, true, 1);
+      break;
+    case 11: GW_WS(__bf16, 32, false, false, 2); break;
+    case 12:
+      if (!band_exp) return hipErrorInvalidValue;
+      GW_WS(_Float16, 32, false, true, 2);
       break;
 #undef GW_WS
     default:
