@@ -42,6 +42,7 @@
 #define GW_H
 
 #include <stddef.h>
+#include <stdint.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -102,6 +103,16 @@ size_t gw_workspace_bytes(const gw_ctx *ctx);
 int gw_tile_count(void);
 const char *gw_tile_name(int tile);
 int gw_default_tile(int precision, int nr);
+
+/* Rate reference for the split-precision update (not a step of the method; for benchmarks that
+ * compare the update with what the matrix cores reach on this device).  Launches `grid`
+ * workgroups of 512 threads; each of the 8 waves runs n_iter iterations of twelve BF16
+ * 32x32x16 MFMAs (12 * 32768 flop) whose operands come from 16 KB of LDS copied from `words`.
+ * The executed flop count is grid * 8 * n_iter * 393216; the caller times the launch on `stream`.
+ *   words  device, 4096 uint32 (2048 BF16 pairs; finite values keep the sums finite), read only
+ *   out    device, grid * 512 floats: one sum per thread, written so the products stay live
+ * Errors: GW_E_INVAL for NULL pointers, n_iter < 1 or grid outside [1, 2^24]. */
+int gw_mfma_rate(gw_ctx *ctx, const uint32_t *words, int n_iter, int grid, float *out, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Orbitals on the grid from their plane-wave coefficients (Sec. 4.1, the

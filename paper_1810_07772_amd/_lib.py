@@ -23,7 +23,7 @@ EXPORTS = ("gw_opts_default", "gw_version", "gw_status_string", "gw_create", "gw
            "gw_polarizability_batched", "gw_autotune", "gw_tail_init", "gw_tail_target", "gw_tail_features",
            "gw_tail_forward", "gw_tail_train_step", "gw_tail_loss", "gw_tail_correct", "gw_newton_inverse",
            "gw_eps_inverse_newton", "gw_orbitals_to_grid",
-           "gw_plasmon_pole", "gw_pp_eps_inverse", "gw_sigma_static", "gw_sigma_sex_modes")
+           "gw_plasmon_pole", "gw_pp_eps_inverse", "gw_sigma_static", "gw_sigma_sex_modes", "gw_mfma_rate")
 TAIL_NWEIGHT, TAIL_NBIAS, TAIL_NPARAM = 21120, 289, 21409
 
 
@@ -99,6 +99,7 @@ def load() -> C.CDLL:
         "gw_pp_eps_inverse": (i, [vp, vp, i, Grid, vp, vp, vp, vp, vp, i, vp, i, vp, vp]),
         "gw_sigma_static": (i, [vp, vp, i, vp, i, Grid, vp, vp, i, vp, vp, vp, vp]),
         "gw_sigma_sex_modes": (i, [vp, vp, i, vp, i, Grid, vp, i, vp, vp, i, vp, vp]),
+        "gw_mfma_rate": (i, [vp, vp, i, i, vp, vp]),
         "gw_orbitals_to_grid": (i, [vp, vp, i, i, Grid, vp, vp, vp]),
         "gw_newton_inverse": (i, [vp, vp, i, d, i, vp, C.POINTER(i), vp, vp]),
         "gw_eps_inverse_newton": (i, [vp, vp, i, Grid, vp, vp, d, d, i, vp, C.POINTER(i), vp, vp]),
@@ -203,6 +204,21 @@ def _grid(n: Sequence[int], a_bohr: float) -> Grid:
 def tile_names():
     lib = load()
     return [lib.gw_tile_name(i).decode() for i in range(lib.gw_tile_count())]
+
+
+def mfma_rate(words, n_iter, grid, out=None, ctx: Optional[Context] = None):
+    """One launch of the MFMA-only rate kernel (gw_mfma_rate): `words` a device int32 tensor of 4096
+    BF16 pairs, `out` grid * 512 floats.  Executed flop: grid * 8 * n_iter * 393216."""
+    import torch
+    if words.numel() != 4096:
+        raise ValueError("words must hold 4096 uint32 words")
+    if out is None:
+        out = torch.empty(int(grid) * 512, dtype=torch.float32, device=words.device)
+    ctx = ctx or context(words.device.index)
+    st = ctx.lib.gw_mfma_rate(ctx.handle, _dev(words, torch.int32, "words"), int(n_iter), int(grid),
+                              _dev(out, torch.float32, "out"), _stream(words))
+    ctx.check(st, "gw_mfma_rate")
+    return out
 
 
 def default_tile_name(precision="fp32", nr=0):

@@ -422,6 +422,15 @@ int gw_tile_count(void) { return herk_tile_count(); }
 const char *gw_tile_name(int t) { return herk_tile_name(t); }
 int gw_default_tile(int precision, int nr) { return herk_default_tile(precision, nr); }
 
+int gw_mfma_rate(gw_ctx *ctx, const uint32_t *words, int n_iter, int grid, float *out, void *stream) {
+  GW_STATUS(begin(ctx));
+  GW_CHECK(ctx, words != nullptr && out != nullptr, "words and out must not be NULL");
+  GW_CHECK(ctx, n_iter >= 1 && grid >= 1 && grid <= (1 << 24), "n_iter must be >= 1 and grid in [1, 2^24]");
+  if (ctx->device < 0) return GW_OK;
+  GW_HIP(ctx, launch_mfma_rate(words, n_iter, grid, out, as_stream(stream)));
+  return GW_OK;
+}
+
 int gw_pair_products(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *psi_c, int nc, int nr,
                      const double *e_v, const double *e_c, double prefactor, gw_c32 *f_out, void *stream) {
   GW_STATUS(begin(ctx));

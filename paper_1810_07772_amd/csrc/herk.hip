@@ -762,6 +762,56 @@ hipError_t launch_band_exponents(const float2 *psi_v, int nv, const float2 *psi_
 }
 
 // ---------------------------------------------------------------------------------------------
+// Rate reference for the split update: MFMA-only waves (two per SIMD, no producers) that take their
+// BF16 operands from 16 KB of LDS filled with the caller's words, twelve 32x32x16 products per
+// iteration over four accumulators.  Under a sustained BF16 MFMA load the chip runs at its power
+// limit, below the clock of the peak figure, so this gives the executed-flop rate a kernel fed from
+// LDS can reach on the same device: 12 * 32768 flop per wave-iteration.
+// ---------------------------------------------------------------------------------------------
+constexpr int RATE_SETS = 16;   // operand sets of 64 lanes x 16 bytes
+
+__global__ __launch_bounds__(2 * NTHR, 2) void mfma_rate_kernel(const u32x4 *__restrict__ words, int n_iter,
+                                                                float *__restrict__ out) {
+  __shared__ u32x4 ops[RATE_SETS * 64];
+  for (int i = threadIdx.x; i < RATE_SETS * 64; i += blockDim.x) ops[i] = words[i];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  typedef SplitTraits<__bf16>::vec vec;
+  f32x16 c0 = {}, c1 = {}, c2 = {}, c3 = {};
+  for (int it = 0; it < n_iter; ++it) {
+    const int k = (2 * it + wave) & (RATE_SETS - 1);
+    const vec a = __builtin_bit_cast(vec, ops[k * 64 + lane]);
+    const vec b = __builtin_bit_cast(vec, ops[((k + 5) & (RATE_SETS - 1)) * 64 + lane]);
+    const vec c = __builtin_bit_cast(vec, ops[((k + 9) & (RATE_SETS - 1)) * 64 + lane]);
+    c0 = SplitTraits<__bf16>::mfma(a, b, c0);
+    c1 = SplitTraits<__bf16>::mfma(a, c, c1);
+    c2 = SplitTraits<__bf16>::mfma(c, b, c2);
+    c3 = SplitTraits<__bf16>::mfma(b, a, c3);
+    c0 = SplitTraits<__bf16>::mfma(a, c, c0);
+    c1 = SplitTraits<__bf16>::mfma(c, b, c1);
+    c2 = SplitTraits<__bf16>::mfma(b, a, c2);
+    c3 = SplitTraits<__bf16>::mfma(a, b, c3);
+    c0 = SplitTraits<__bf16>::mfma(c, b, c0);
+    c1 = SplitTraits<__bf16>::mfma(b, a, c1);
+    c2 = SplitTraits<__bf16>::mfma(a, b, c2);
+    c3 = SplitTraits<__bf16>::mfma(a, c, c3);
+  }
+  float r = 0.f;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) r += c0[e] + c1[e] + c2[e] + c3[e];
+  out[(size_t)blockIdx.x * (2 * NTHR) + threadIdx.x] = r;
+}
+
+size_t mfma_rate_words() { return (size_t)RATE_SETS * 64 * 4; }
+int mfma_rate_block() { return 2 * NTHR; }
+
+hipError_t launch_mfma_rate(const unsigned *words, int n_iter, int grid, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(mfma_rate_kernel, dim3(grid), dim3(2 * NTHR), 0, s, reinterpret_cast<const u32x4 *>(words),
+                     n_iter, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
 // Tile table and dispatch
 // ---------------------------------------------------------------------------------------------
 struct TileCfg { const char *name; int precision; };

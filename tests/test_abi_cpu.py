@@ -165,6 +165,10 @@ def test_dry_run_other_entry_points(gw):
     assert sg(sx=None, ss=None) == 1 and sg(ei=None) == 1 and sg(nn=0) == 1 and sg(nn=257) == 1 and sg(nv=0) == 1
     assert lib.gw_sigma_sex_modes(h, vp(), 4, vp(), 3, grid, pm, len(m), vp(), vp(), 5, vp(), None) == 0
     assert lib.gw_sigma_sex_modes(h, vp(), 4, vp(), 3, grid, pm, len(m), vp(), vp(), 0, vp(), None) == 1
+    # MFMA rate reference
+    assert lib.gw_mfma_rate(h, vp(), 10, 256, vp(), None) == 0
+    assert lib.gw_mfma_rate(h, vp(0), 10, 256, vp(), None) == 1 and lib.gw_mfma_rate(h, vp(), 10, 256, vp(0), None) == 1
+    assert lib.gw_mfma_rate(h, vp(), 0, 256, vp(), None) == 1 and lib.gw_mfma_rate(h, vp(), 10, 0, vp(), None) == 1
     # Newton iteration arguments
     its = C.c_int(-1)
     assert lib.gw_newton_inverse(h, vp(), 10, 1e-11, 50, vp(), C.byref(its), None, None) == 0 and its.value == 0

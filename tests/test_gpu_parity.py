@@ -299,3 +299,25 @@ def test_split_two_level_sum(gw, prec, tile_name, tol, nv, nc):
     e2 = orc.rel_f(p.cpu().numpy(), ref)
     print(f"accumulated in two calls: rel_F(P) = {e2:.2e}")
     assert e2 < tol
+
+
+def test_mfma_rate_reference_runs_its_products(gw):
+    """The MFMA-only rate kernel does the products it counts: the sum of all accumulator entries of a
+    wave equals sum over iterations of 3 (v_a.v_b + v_a.v_c + v_c.v_b + v_b.v_a), where v_X[k] sums
+    operand set X over the lanes holding K index k (lanes 0-31: k = 0..7, lanes 32-63: k = 8..15)."""
+    rng = np.random.default_rng(3)
+    halves = ((127 << 7) | rng.integers(0, 128, 8192)).astype(np.uint32)   # BF16 in [1, 2): no cancellation
+    words = torch.from_numpy((halves[0::2] | (halves[1::2] << 16)).view(np.int32).copy()).to("cuda:0")
+    grid, n_iter = 3, 20
+    out = gw.mfma_rate(words, n_iter, grid).cpu().numpy().astype(np.float64)
+    sets = (halves.astype(np.uint32) << 16).view(np.float32).astype(np.float64).reshape(16, 64, 8)
+    v = np.concatenate([sets[:, :32, :].sum(axis=1), sets[:, 32:, :].sum(axis=1)], axis=1)   # [set][k]
+    per_wg = 0.0
+    for w in range(8):
+        for it in range(n_iter):
+            a = (2 * it + w) & 15
+            b, c = (a + 5) & 15, (a + 9) & 15
+            per_wg += 3 * (v[a] @ v[b] + v[a] @ v[c] + v[c] @ v[b] + v[b] @ v[a])
+    got = out.reshape(grid, 512).sum(axis=1)
+    print(f"per-workgroup sums {got}, expected {per_wg:.6e}")
+    assert np.all(np.abs(got - per_wg) < 1e-5 * per_wg)
