@@ -264,13 +264,21 @@ template <> struct SplitTraits<_Float16> {
   }
 };
 
-// (re, im) words -> (im, -re) words.
+// (re, im) words -> (im, -re) words: one packed 16-bit add whose operand selects swap the halves
+// of w and add (0, 0x8000), which flips the sign bit of the new high half (the add wraps mod 2^16).
+// The compiler writes this as a shift and an xor; the single instruction halves the VALU work of
+// the MFMA waves' rotation.  It is an integer op on 16-bit lanes, not packed FP32 arithmetic.
+__device__ __forceinline__ unsigned rot_word(unsigned w) {
+  unsigned r;
+  asm("v_pk_add_u16 %0, %1, %2 op_sel:[1,0] op_sel_hi:[0,1]" : "=v"(r) : "v"(w), "s"(0x80000000u));
+  return r;
+}
 template <typename V>
 __device__ __forceinline__ V rot_neg(V b) {
   u32x4 w = __builtin_bit_cast(u32x4, b);
   u32x4 y;
 #pragma unroll
-  for (int m = 0; m < 4; ++m) y[m] = ((w[m] >> 16) | (w[m] << 16)) ^ 0x80000000u;
+  for (int m = 0; m < 4; ++m) y[m] = rot_word(w[m]);
   return __builtin_bit_cast(V, y);
 }
 
