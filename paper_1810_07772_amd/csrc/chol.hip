@@ -32,9 +32,10 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int M, int N, int K, const d
     kend = min(K, (int)(blockIdx.z + 1) * kchunk);
   }
   if (lower_only && col0 >= row0 + GT) return;
-  __shared__ double sA[GK][2][GT];
-  __shared__ double sX[GK][2][GT];
-  __shared__ double sY[GK][2][GT];
+  // two LDS stages: the global loads of stage k+1 are in flight in registers while stage k's MFMAs run
+  __shared__ double sA[2][GK][2][GT];
+  __shared__ double sX[2][GK][2][GT];
+  __shared__ double sY[2][GK][2][GT];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
   f64x4 accR[2][2], accI[2][2];
@@ -48,40 +49,65 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int M, int N, int K, const d
   int kbeg = kchunk > 0 ? (int)blockIdx.z * kchunk : 0;
   if (tri_k) kbeg = (max(row0, col0) / GK) * GK;
   const int kl = lane >> 4, li = lane & 15;
-  for (int k0 = kbeg; k0 < kend; k0 += GK) {
+  constexpr int PER = (GT * GK) / 256;   // elements of each operand per thread and stage
+  double2 va[PER], vb[PER];
+  // element idx of a stage: A row r / B column c and its k offset kk, in the order that keeps the
+  // global reads contiguous for either layout
+  auto a_coord = [&](int idx, int &r, int &kk) {
+    if (transA) { r = idx % GT; kk = idx / GT; } else { r = idx / GK; kk = idx % GK; }
+  };
+  auto b_coord = [&](int idx, int &c, int &kk) {
+    if (transB) { c = idx / GK; kk = idx % GK; } else { c = idx % GT; kk = idx / GT; }
+  };
+  auto gload = [&](int k0) {
 #pragma unroll
-    for (int it = 0; it < (GT * GK) / 256; ++it) {
+    for (int it = 0; it < PER; ++it) {
       const int idx = tid + it * 256;
-      // A side
-      int r, kk;
-      if (transA) { r = idx % GT; kk = idx / GT; } else { r = idx / GK; kk = idx % GK; }
-      double2 va = make_double2(0.0, 0.0);
+      int r, c, kk;
+      a_coord(idx, r, kk);
+      va[it] = make_double2(0.0, 0.0);
       if (row0 + r < M && k0 + kk < kend) {
-        if (transA) { va = A[(long long)(k0 + kk) * lda + row0 + r]; va.y = -va.y; }
-        else va = A[(long long)(row0 + r) * lda + k0 + kk];
+        if (transA) { va[it] = A[(long long)(k0 + kk) * lda + row0 + r]; va[it].y = -va[it].y; }
+        else va[it] = A[(long long)(row0 + r) * lda + k0 + kk];
       }
-      sA[kk][0][r] = va.x;
-      sA[kk][1][r] = va.y;
-      // B side
-      int c;
-      if (transB) { c = idx / GK; kk = idx % GK; } else { c = idx % GT; kk = idx / GT; }
-      double2 vb = make_double2(0.0, 0.0);
+      b_coord(idx, c, kk);
+      vb[it] = make_double2(0.0, 0.0);
       if (col0 + c < N && k0 + kk < kend) {
-        if (transB) { vb = B[(long long)(col0 + c) * ldb + k0 + kk]; vb.y = -vb.y; }
-        else vb = B[(long long)(k0 + kk) * ldb + col0 + c];
+        if (transB) { vb[it] = B[(long long)(col0 + c) * ldb + k0 + kk]; vb[it].y = -vb[it].y; }
+        else vb[it] = B[(long long)(k0 + kk) * ldb + col0 + c];
       }
-      sX[kk][0][c] = vb.x;
-      sX[kk][1][c] = -vb.y;
-      sY[kk][0][c] = vb.y;
-      sY[kk][1][c] = vb.x;
     }
-    __syncthreads();
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int idx = tid + it * 256;
+      int r, c, kk;
+      a_coord(idx, r, kk);
+      sA[buf][kk][0][r] = va[it].x;
+      sA[buf][kk][1][r] = va[it].y;
+      b_coord(idx, c, kk);
+      sX[buf][kk][0][c] = vb[it].x;
+      sX[buf][kk][1][c] = -vb[it].y;
+      sY[buf][kk][0][c] = vb[it].y;
+      sY[buf][kk][1][c] = vb[it].x;
+    }
+  };
+  int buf = 0;
+  if (kbeg < kend) {
+    gload(kbeg);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += GK) {
+    const bool more = k0 + GK < kend;
+    if (more) gload(k0 + GK);
 #pragma unroll
     for (int s = 0; s < GK / 2; ++s) {
       const int kk = 2 * s + (kl >> 1), comp = kl & 1;
-      const double a0 = sA[kk][comp][wr * 32 + li], a1 = sA[kk][comp][wr * 32 + 16 + li];
-      const double x0 = sX[kk][comp][wc * 32 + li], x1 = sX[kk][comp][wc * 32 + 16 + li];
-      const double y0 = sY[kk][comp][wc * 32 + li], y1 = sY[kk][comp][wc * 32 + 16 + li];
+      const double a0 = sA[buf][kk][comp][wr * 32 + li], a1 = sA[buf][kk][comp][wr * 32 + 16 + li];
+      const double x0 = sX[buf][kk][comp][wc * 32 + li], x1 = sX[buf][kk][comp][wc * 32 + 16 + li];
+      const double y0 = sY[buf][kk][comp][wc * 32 + li], y1 = sY[buf][kk][comp][wc * 32 + 16 + li];
       accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0, accR[0][0], 0, 0, 0);
       accI[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, y0, accI[0][0], 0, 0, 0);
       accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x1, accR[0][1], 0, 0, 0);
@@ -91,7 +117,9 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int M, int N, int K, const d
       accR[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1, accR[1][1], 0, 0, 0);
       accI[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, y1, accI[1][1], 0, 0, 0);
     }
+    if (more) lstore(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
   // lane holds D[i][j] of each 16x16 block in register e with i = 4*e + (lane>>4), j = lane & 15
 #pragma unroll
