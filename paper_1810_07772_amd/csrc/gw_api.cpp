@@ -437,7 +437,7 @@ int gw_pair_products(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *psi
   GW_STATUS(check_bands(ctx, psi_v, nv, psi_c, nc, nr));
   GW_CHECK(ctx, f_out != nullptr, "f_out must not be NULL");
   GW_CHECK(ctx, std::isfinite(prefactor) && prefactor > 0.0, "prefactor must be positive");
-  GW_CHECK(ctx, nc <= 2147483647 && (nr + 511) / 512 <= 65535, "nr too large for the pair-product grid");
+  GW_CHECK(ctx, (nc + 7) / 8 <= 65535, "nc too large for the pair-product grid");
   GW_STATUS(check_energies(ctx, e_v, nv, e_c, nc));
   if (ctx->device < 0) return GW_OK;
   hipStream_t s = as_stream(stream);
