@@ -337,25 +337,40 @@ size_t chol_small_bytes(int n) {
 
 hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small, int *pivot_dev, double2 *out,
                        hipStream_t s) {
-  const int nblk = (n + NB - 1) / NB;
   const size_t nn = (size_t)n * n;
   const unsigned fill_blocks = (unsigned)((nn + 255) / 256);
   GW_TRY(launch_fill_int(pivot_dev, 0, s));
   hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, l, n, 0.0);
   GW_TRY(hipGetLastError());
+  // Panels of PW columns: inside a panel each NB-wide step updates only the panel's columns; one
+  // K = PW product then updates everything right of (factorisation) or below (substitution) the panel,
+  // so the large trailing matrix is read and written once per panel instead of once per NB step.
+  constexpr int PW = 128;   // 128, 256 and 512 measured alike; 32 (no panels) 5% slower at N = 4067
   // 1. factor a = L L^H
-  for (int kb = 0; kb < nblk; ++kb) {
-    const int k0 = kb * NB, nb = min(NB, n - k0), rest = n - k0 - nb;
-    double2 *linv = small + (size_t)kb * NB * NB;
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, a, n, k0, l, linv, pivot_dev);
-    GW_TRY(hipGetLastError());
+  for (int p0 = 0; p0 < n; p0 += PW) {
+    const int p1 = min(n, p0 + PW);
+    for (int k0 = p0; k0 < p1; k0 += NB) {
+      const int kb = k0 / NB, nb = min(NB, n - k0), rest = n - k0 - nb;
+      double2 *linv = small + (size_t)kb * NB * NB;
+      hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, a, n, k0, l, linv, pivot_dev);
+      GW_TRY(hipGetLastError());
+      if (rest > 0) {
+        // panel column: L[k0+nb:, k0:k0+nb] = A[k0+nb:, k0:k0+nb] Linv^H
+        GW_TRY(zgemm(rest, nb, nb, a + (size_t)(k0 + nb) * n + k0, n, 0, linv, NB, 1, l + (size_t)(k0 + nb) * n + k0,
+                     n, 1.0, 0.0, 0, 0, s));
+        // the rest of this panel's columns: A[k0+nb:, k0+nb:p1] -= Lp Lp[k0+nb:p1]^H
+        const double2 *lp = l + (size_t)(k0 + nb) * n + k0;
+        const int wcols = p1 - (k0 + nb);
+        if (wcols > 0)
+          GW_TRY(zgemm(rest, wcols, nb, lp, n, 0, lp, n, 1, a + (size_t)(k0 + nb) * n + k0 + nb, n, -1.0, 1.0, 1, 0,
+                       s));
+      }
+    }
+    // right of the panel: A[p1:, p1:] -= L[p1:, p0:p1] L[p1:, p0:p1]^H (lower tiles)
+    const int rest = n - p1;
     if (rest > 0) {
-      // panel: L[k0+nb:, k0:k0+nb] = A[k0+nb:, k0:k0+nb] Linv^H
-      GW_TRY(zgemm(rest, nb, nb, a + (size_t)(k0 + nb) * n + k0, n, 0, linv, NB, 1, l + (size_t)(k0 + nb) * n + k0, n,
-                   1.0, 0.0, 0, 0, s));
-      // trailing: A[k0+nb:, k0+nb:] -= Lp Lp^H (lower tiles)
-      const double2 *lp = l + (size_t)(k0 + nb) * n + k0;
-      GW_TRY(zgemm(rest, rest, nb, lp, n, 0, lp, n, 1, a + (size_t)(k0 + nb) * n + k0 + nb, n, -1.0, 1.0, 1, 0, s));
+      const double2 *lp = l + (size_t)p1 * n + p0;
+      GW_TRY(zgemm(rest, rest, p1 - p0, lp, n, 0, lp, n, 1, a + (size_t)p1 * n + p1, n, -1.0, 1.0, 1, 0, s));
     }
   }
   // 2. X = L^-1 by right-looking block substitution on B = I (B reuses a)
@@ -363,16 +378,24 @@ hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small
   GW_TRY(hipGetLastError());
   hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, x, n, 0.0);
   GW_TRY(hipGetLastError());
-  for (int kb = 0; kb < nblk; ++kb) {
-    const int k0 = kb * NB, nb = min(NB, n - k0), rest = n - k0 - nb, ncol = k0 + nb;
-    const double2 *linv = small + (size_t)kb * NB * NB;
-    // X_k = Linv_kk B_k (block row k, columns < k0+nb)
-    GW_TRY(zgemm(nb, ncol, nb, linv, NB, 0, a + (size_t)k0 * n, n, 0, x + (size_t)k0 * n, n, 1.0, 0.0, 0, 0, s));
-    if (rest > 0) {
-      // B_i -= L_ik X_k for the block rows below
-      GW_TRY(zgemm(rest, ncol, nb, l + (size_t)(k0 + nb) * n + k0, n, 0, x + (size_t)k0 * n, n, 0,
-                   a + (size_t)(k0 + nb) * n, n, -1.0, 1.0, 0, 0, s));
+  for (int p0 = 0; p0 < n; p0 += PW) {
+    const int p1 = min(n, p0 + PW);
+    for (int k0 = p0; k0 < p1; k0 += NB) {
+      const int kb = k0 / NB, nb = min(NB, n - k0), ncol = k0 + nb;
+      const double2 *linv = small + (size_t)kb * NB * NB;
+      // X_k = Linv_kk B_k (block row k, columns < k0+nb)
+      GW_TRY(zgemm(nb, ncol, nb, linv, NB, 0, a + (size_t)k0 * n, n, 0, x + (size_t)k0 * n, n, 1.0, 0.0, 0, 0, s));
+      // B_i -= L_ik X_k for the block rows below inside the panel
+      const int wrows = p1 - (k0 + nb);
+      if (wrows > 0)
+        GW_TRY(zgemm(wrows, ncol, nb, l + (size_t)(k0 + nb) * n + k0, n, 0, x + (size_t)k0 * n, n, 0,
+                     a + (size_t)(k0 + nb) * n, n, -1.0, 1.0, 0, 0, s));
     }
+    // below the panel: B[p1:, :p1] -= L[p1:, p0:p1] X[p0:p1, :p1]
+    const int rest = n - p1;
+    if (rest > 0)
+      GW_TRY(zgemm(rest, p1, p1 - p0, l + (size_t)p1 * n + p0, n, 0, x + (size_t)p0 * n, n, 0, a + (size_t)p1 * n, n,
+                   -1.0, 1.0, 0, 0, s));
   }
   // 3. out = X^H X (lower tiles, k from max(row, col) since X is lower triangular), then mirror
   GW_TRY(zgemm(n, n, n, x, n, 1, x, n, 0, out, n, 1.0, 0.0, 1, 1, s));
