@@ -75,9 +75,7 @@ hipError_t launch_band_exponents(const float2 *psi_v, int nv, const float2 *psi_
                                  const float *scale, int ldsc, int *band_exp, hipStream_t s);
 // ints needed by launch_band_exponents' buffer (exponents, band order, sorted exponents, row maxima)
 size_t band_exp_ints(int nv, int nc);
-// MFMA-only rate kernel: operand words it reads (uint32), threads per workgroup, launch.
-size_t mfma_rate_words();
-int mfma_rate_block();
+// MFMA-only rate kernel (4096 uint32 operand words, grid workgroups of 512 threads).
 hipError_t launch_mfma_rate(const unsigned *words, int n_iter, int grid, float *out, hipStream_t s);
 
 // FFT helpers.

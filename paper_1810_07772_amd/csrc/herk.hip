@@ -810,9 +810,6 @@ __global__ __launch_bounds__(2 * NTHR, 2) void mfma_rate_kernel(const u32x4 *__r
   out[(size_t)blockIdx.x * (2 * NTHR) + threadIdx.x] = r;
 }
 
-size_t mfma_rate_words() { return (size_t)RATE_SETS * 64 * 4; }
-int mfma_rate_block() { return 2 * NTHR; }
-
 hipError_t launch_mfma_rate(const unsigned *words, int n_iter, int grid, float *out, hipStream_t s) {
   hipLaunchKernelGGL(mfma_rate_kernel, dim3(grid), dim3(2 * NTHR), 0, s, reinterpret_cast<const u32x4 *>(words),
                      n_iter, out);
