@@ -99,6 +99,13 @@ __global__ void start_block_kernel(double2 *__restrict__ x, int ng, int b, unsig
 // columns of z (row-major, leading dimension ldz).
 constexpr int JMAX = 32;
 
+// Sum of v over the 64 lanes of a wave.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __global__ __launch_bounds__(256) void herm_jacobi_kernel(const double2 *__restrict__ h, int b, int ldh,
                                                           double *__restrict__ evals, double2 *__restrict__ z,
                                                           int ldz, int max_sweeps) {
@@ -107,10 +114,10 @@ __global__ __launch_bounds__(256) void herm_jacobi_kernel(const double2 *__restr
   __shared__ double rc[JMAX / 2], rs[JMAX / 2];
   __shared__ double2 rph[JMAX / 2];
   __shared__ int rp[JMAX / 2], rq[JMAX / 2];
-  __shared__ double red[256];
+  __shared__ double red_off[4], red_all[4];
   __shared__ int perm[JMAX];
   __shared__ int stop;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = (b + 1) & ~1;          // even size; a padding index has a zero row and column
   for (int idx = tid; idx < JMAX * JMAX; idx += 256) {
     const int i = idx / JMAX, j = idx % JMAX;
@@ -134,21 +141,16 @@ __global__ __launch_bounds__(256) void herm_jacobi_kernel(const double2 *__restr
       all += s2;
       if (i != j) off += s2;
     }
-    red[tid] = off;
+    // wave sums, then the four waves' partials
+    off = wave_sum(off);
+    all = wave_sum(all);
+    if (lane == 0) { red_off[wave] = off; red_all[wave] = all; }
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (tid < st) red[tid] += red[tid + st];
-      __syncthreads();
+    if (tid == 0) {
+      const double o = red_off[0] + red_off[1] + red_off[2] + red_off[3];
+      const double a = red_all[0] + red_all[1] + red_all[2] + red_all[3];
+      stop = (o <= 1e-30 * a) || a == 0.0;   // off-diagonal norm below 1e-15 relative
     }
-    const double off_sum = red[0];
-    __syncthreads();
-    red[tid] = all;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (tid < st) red[tid] += red[tid + st];
-      __syncthreads();
-    }
-    if (tid == 0) stop = (off_sum <= 1e-30 * red[0]) || red[0] == 0.0;   // off-diagonal norm below 1e-15 relative
     __syncthreads();
     if (stop) break;
     for (int round = 0; round < m - 1; ++round) {
