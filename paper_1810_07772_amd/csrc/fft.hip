@@ -197,6 +197,47 @@ __global__ __launch_bounds__(FFT_THREADS) void fft_gather_pass_kernel(const floa
   for (int k = 0; k < N; ++k) out[((long long)(o * N + k) * U + u) * ld_out + b] = X[k];
 }
 
+// The gather pass along the last axis (U = 1) with its output transposed on the way: 64 batch columns
+// (bands) and 4 consecutive lines per workgroup; each thread transforms one line into an LDS tile, and
+// the workgroup then writes each band's 4 N consecutive outputs to its own row, out[b][o N + k].  This
+// replaces a [grid][band] intermediate and a separate transpose of it.
+constexpr int GT_BANDS = 64, GT_LINES = FFT_THREADS / GT_BANDS;
+template <int N, int SIGN>
+__global__ __launch_bounds__(FFT_THREADS) void fft_gather_pass_t_kernel(const float2 *__restrict__ in,
+                                                                         float2 *__restrict__ out, int O, int B,
+                                                                         long long ld_in, long long ld_out,
+                                                                         const int *__restrict__ map, float scale) {
+  __shared__ float2 tile[GT_LINES * N][GT_BANDS + 1];
+  const int tb = threadIdx.x % GT_BANDS, l = threadIdx.x / GT_BANDS;
+  const int b0 = blockIdx.x * GT_BANDS, b = b0 + tb;
+  const int o0 = blockIdx.y * GT_LINES, o = o0 + l;
+  if (o < O) {
+    const int *mrow = map + (size_t)o * N;
+    float2 x[N], X[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int row = mrow[i];
+      float2 v = make_float2(0.f, 0.f);
+      if (row >= 0 && b < B) {
+        v = in[(long long)row * ld_in + b];
+        v.x *= scale;
+        v.y *= scale;
+      }
+      x[i] = v;
+    }
+    dft_regs<N, SIGN>(x, X);
+#pragma unroll
+    for (int k = 0; k < N; ++k) tile[l * N + k][tb] = X[k];
+  }
+  __syncthreads();
+  const int nl = min(GT_LINES, O - o0), nb = min(GT_BANDS, B - b0);
+  const int run = nl * N;                       // consecutive outputs per band in this block
+  for (int v = threadIdx.x; v < nb * run; v += FFT_THREADS) {
+    const int band = v / run, kk = v - band * run;
+    out[(long long)(b0 + band) * ld_out + (long long)o0 * N + kk] = tile[kk][band];
+  }
+}
+
 #define GW_FFT_SIZES(X) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16) X(18) X(20) X(24) X(27) X(30) X(32) X(36) X(40) X(48)
 
 bool fft_size_supported(int n) {
@@ -244,6 +285,27 @@ hipError_t launch_fft_gather_pass(int n, int sign, const float2 *in, float2 *out
     else                                                                                                       \
       hipLaunchKernelGGL(HIP_KERNEL_NAME(fft_gather_pass_kernel<n_, 1>), grid, block, 0, s, in, out, U, B,    \
                          ld_in, ld_out, map, scale);                                                           \
+    break;
+    GW_FFT_SIZES(GW_CASE)
+#undef GW_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_gather_pass_t(int n, int sign, const float2 *in, float2 *out, int O, int B, long long ld_in,
+                                    long long ld_out, const int *map, float scale, hipStream_t s) {
+  dim3 grid((B + GT_BANDS - 1) / GT_BANDS, (O + GT_LINES - 1) / GT_LINES), block(FFT_THREADS);
+  if (grid.y > 65535) return hipErrorInvalidValue;
+  switch (n) {
+#define GW_CASE(n_)                                                                                             \
+  case n_:                                                                                                      \
+    if (sign < 0)                                                                                               \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(fft_gather_pass_t_kernel<n_, -1>), grid, block, 0, s, in, out, O, B,  \
+                         ld_in, ld_out, map, scale);                                                            \
+    else                                                                                                        \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(fft_gather_pass_t_kernel<n_, 1>), grid, block, 0, s, in, out, O, B,   \
+                         ld_in, ld_out, map, scale);                                                            \
     break;
     GW_FFT_SIZES(GW_CASE)
 #undef GW_CASE

@@ -490,26 +490,26 @@ int gw_orbitals_to_grid(gw_ctx *ctx, const gw_c32 *coeff, int nb, int npw, gw_gr
   SpherePlan p;
   int *dA, *dB, *dC;
   GW_STATUS(upload_plan(ctx, grid, pw_miller, npw, WS_ORB_MAP, p, &dA, &dB, &dC, s));
-  // band chunk: the largest intermediate ([nr][w]) stays near 1 GiB
+  // band chunk: an intermediate of [nr][w] elements would stay near 1 GiB
   const int w = (int)std::min<long long>(nb, std::max<long long>(64, (1LL << 27) / nr));
   const size_t rows1 = (size_t)p.n1 * p.n2 * p.m3count, rows2 = (size_t)p.n1 * p.npair;
-  void *ct, *a1, *a2, *rt;
+  GW_CHECK(ctx, ((long long)p.n1 * p.n2 + 3) / 4 <= 65535, "grid too large for the orbital transform");
+  void *ct, *a1, *a2;
   GW_STATUS(ws_get(ctx, WS_ORB_T, (size_t)npw * w * sizeof(float2), &ct, s));
   GW_STATUS(ws_get(ctx, WS_ORB_A1, rows1 * w * sizeof(float2), &a1, s));
   GW_STATUS(ws_get(ctx, WS_ORB_A2, rows2 * w * sizeof(float2), &a2, s));
-  GW_STATUS(ws_get(ctx, WS_ORB_R, (size_t)nr * w * sizeof(float2), &rt, s));
   const float scale = (float)(1.0 / std::sqrt((double)nr));
   const float2 *c = (const float2 *)coeff;
   float2 *out = (float2 *)psi;
   for (int b0 = 0; b0 < nb; b0 += w) {
     const int bw = std::min(w, nb - b0);
-    float2 *t = (float2 *)ct, *x1 = (float2 *)a1, *x2 = (float2 *)a2, *r = (float2 *)rt;
+    float2 *t = (float2 *)ct, *x1 = (float2 *)a1, *x2 = (float2 *)a2;
     GW_HIP(ctx, launch_transpose_c64(c + (size_t)b0 * npw, t, bw, npw, npw, bw, s));
     // sphere -> (i1, pair) along axis 1; -> (i1, i2, m3) along axis 2; -> grid along axis 3
     GW_HIP(ctx, launch_fft_gather_pass(p.n1, +1, t, x2, 1, p.npair, bw, bw, bw, dC, scale, s));
     GW_HIP(ctx, launch_fft_gather_pass(p.n2, +1, x2, x1, p.n1, p.m3count, bw, bw, bw, dB, 1.0f, s));
-    GW_HIP(ctx, launch_fft_gather_pass(p.n3, +1, x1, r, p.n1 * p.n2, 1, bw, bw, bw, dA, 1.0f, s));
-    GW_HIP(ctx, launch_transpose_c64(r, out + (size_t)b0 * nr, nr, bw, bw, nr, s));
+    // the last axis writes the band-major orbitals directly
+    GW_HIP(ctx, launch_fft_gather_pass_t(p.n3, +1, x1, out + (size_t)b0 * nr, p.n1 * p.n2, bw, bw, nr, dA, 1.0f, s));
   }
   return GW_OK;
 }

@@ -50,7 +50,6 @@ enum SlotId {
   WS_ORB_T,       // plane-wave coefficients, transposed [npw][nb]
   WS_ORB_A1,      // orbital transform intermediates
   WS_ORB_A2,
-  WS_ORB_R,       // orbitals [nr][nb] before the final transpose
   WS_ORB_MAP,     // int maps of the orbital transform
   WS_COUNT_BASE
 };
@@ -85,6 +84,9 @@ bool fft_size_supported(int n);
 hipError_t launch_fft_pass(int n, int sign, const float2 *in, float2 *out, int O, int U, int B, long long ld_in,
                            long long ld_out, const int *map, hipStream_t s);
 // Gather pass: rows of `in` read through `map` (-1 reads zero) and scaled, outputs to rows (o*n + k)*U + u.
+// The gather pass along the last axis (U = 1) writing out[b][o n + k] directly (band-major output).
+hipError_t launch_fft_gather_pass_t(int n, int sign, const float2 *in, float2 *out, int O, int B, long long ld_in,
+                                    long long ld_out, const int *map, float scale, hipStream_t s);
 hipError_t launch_fft_gather_pass(int n, int sign, const float2 *in, float2 *out, int O, int U, int B, long long ld_in,
                                   long long ld_out, const int *map, float scale, hipStream_t s);
 hipError_t launch_transpose_c64(const float2 *in, float2 *out, int rows, int cols, long long ld_in,
