@@ -203,7 +203,10 @@ hipError_t launch_zgemm(int M, int N, int K, const double2 *A, long long lda, in
   return zgemm(M, N, K, A, lda, transA, B, ldb, transB, C, ldc, alpha, beta, 0, 0, s);
 }
 
-// ---- diagonal block: L_kk = chol(A_kk) and Linv_kk = L_kk^-1 (one workgroup) ------------------
+// ---- diagonal block L_kk = chol(A_kk), Linv_kk = L_kk^-1, and the panel column below it -------------
+// Every workgroup factors and inverts the 32 x 32 block in LDS (cheap, and it saves a dependent launch
+// per step); workgroup 0 stores L_kk, Linv_kk and the pivot flag, and workgroup g forms 64 rows of the
+// panel L[k0+nb+64g : +64, k0 : k0+nb] = A Linv_kk^H.
 constexpr int NB = 32;
 
 __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restrict__ A, int n, int k0,
@@ -286,12 +289,36 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
     }
   }
   __syncthreads();
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int i = idx / NB, j = idx % NB;
-    if (i < nb && j < nb) L[(size_t)(k0 + i) * n + k0 + j] = (j <= i) ? a[i][j] : make_double2(0.0, 0.0);
-    linv[idx] = (i < nb && j < nb) ? x[i][j] : make_double2(0.0, 0.0);
+  if (blockIdx.x == 0) {
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+      const int i = idx / NB, j = idx % NB;
+      if (i < nb && j < nb) L[(size_t)(k0 + i) * n + k0 + j] = (j <= i) ? a[i][j] : make_double2(0.0, 0.0);
+      linv[idx] = (i < nb && j < nb) ? x[i][j] : make_double2(0.0, 0.0);
+    }
+    if (tid == 0 && bad != 0 && *pivot == 0) *pivot = bad;
   }
-  if (tid == 0 && bad != 0 && *pivot == 0) *pivot = bad;
+  // panel below the block, 64 rows per workgroup (every workgroup factored the block above for itself):
+  // L[r][k0 + j] = sum_{k <= j} A[r][k0 + k] conj(Linv[j][k])
+  const int r0 = k0 + nb + (int)blockIdx.x * 64;
+  if (r0 >= n) return;
+  __shared__ double2 pa[64][NB + 1];
+  for (int idx = tid; idx < 64 * NB; idx += 256) {
+    const int i = idx / NB, k = idx % NB;
+    pa[i][k] = (r0 + i < n && k < nb) ? A[(size_t)(r0 + i) * n + k0 + k] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < 64 * NB; idx += 256) {
+    const int i = idx / NB, j = idx % NB;
+    if (r0 + i < n && j < nb) {
+      double sr = 0.0, si = 0.0;
+      for (int k = 0; k <= j; ++k) {
+        const double2 av = pa[i][k], v = x[j][k];
+        sr += av.x * v.x + av.y * v.y;
+        si += av.y * v.x - av.x * v.y;
+      }
+      L[(size_t)(r0 + i) * n + k0 + j] = make_double2(sr, si);
+    }
+  }
 }
 
 __global__ void fill_identity_kernel(double2 *__restrict__ a, int n, double diag) {
@@ -352,12 +379,11 @@ hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small
     for (int k0 = p0; k0 < p1; k0 += NB) {
       const int kb = k0 / NB, nb = min(NB, n - k0), rest = n - k0 - nb;
       double2 *linv = small + (size_t)kb * NB * NB;
-      hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, a, n, k0, l, linv, pivot_dev);
+      // the diagonal block and, in the same launch, the panel column L[k0+nb:, k0:k0+nb] = A Linv^H
+      hipLaunchKernelGGL(potrf_diag_kernel, dim3(std::max(1, (rest + 63) / 64)), dim3(256), 0, s, a, n, k0, l, linv,
+                         pivot_dev);
       GW_TRY(hipGetLastError());
       if (rest > 0) {
-        // panel column: L[k0+nb:, k0:k0+nb] = A[k0+nb:, k0:k0+nb] Linv^H
-        GW_TRY(zgemm(rest, nb, nb, a + (size_t)(k0 + nb) * n + k0, n, 0, linv, NB, 1, l + (size_t)(k0 + nb) * n + k0,
-                     n, 1.0, 0.0, 0, 0, s));
         // the rest of this panel's columns: A[k0+nb:, k0+nb:p1] -= Lp Lp[k0+nb:p1]^H
         const double2 *lp = l + (size_t)(k0 + nb) * n + k0;
         const int wcols = p1 - (k0 + nb);
