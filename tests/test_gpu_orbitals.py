@@ -25,7 +25,8 @@ def c64(x):
     return torch.from_numpy(np.ascontiguousarray(np.asarray(x).astype(np.complex64))).to("cuda:0")
 
 
-@pytest.mark.parametrize("n,r2,nb", [((8, 8, 8), 6.0, 16), ((12, 10, 9), 8.0, 37), ((16, 16, 16), 20.0, 300)])
+@pytest.mark.parametrize("n,r2,nb", [((8, 8, 8), 6.0, 16), ((12, 10, 9), 8.0, 37), ((16, 16, 16), 20.0, 300),
+                                     ((9, 5, 8), 3.0, 70)])   # 45 lines (a partial block of 4) and 64 + 6 bands
 def test_small_grids_full(gw, n, r2, nb):
     # FP32 transform: about a dozen roundings of 6e-8 per output, so 1e-6 relative
     rng = np.random.default_rng(sum(n))
