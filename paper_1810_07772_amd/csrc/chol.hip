@@ -59,6 +59,8 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int M, int N, int K, const d
   auto b_coord = [&](int idx, int &c, int &kk) {
     if (transB) { c = idx / GK; kk = idx % GK; } else { c = idx % GT; kk = idx / GT; }
   };
+  // Loads keep the raw values; the conjugation of a transposed operand is applied when they are
+  // written to LDS, so no instruction waits on a load before the stage's MFMAs have been issued.
   auto gload = [&](int k0) {
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
@@ -66,16 +68,12 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int M, int N, int K, const d
       int r, c, kk;
       a_coord(idx, r, kk);
       va[it] = make_double2(0.0, 0.0);
-      if (row0 + r < M && k0 + kk < kend) {
-        if (transA) { va[it] = A[(long long)(k0 + kk) * lda + row0 + r]; va[it].y = -va[it].y; }
-        else va[it] = A[(long long)(row0 + r) * lda + k0 + kk];
-      }
+      if (row0 + r < M && k0 + kk < kend)
+        va[it] = transA ? A[(long long)(k0 + kk) * lda + row0 + r] : A[(long long)(row0 + r) * lda + k0 + kk];
       b_coord(idx, c, kk);
       vb[it] = make_double2(0.0, 0.0);
-      if (col0 + c < N && k0 + kk < kend) {
-        if (transB) { vb[it] = B[(long long)(col0 + c) * ldb + k0 + kk]; vb[it].y = -vb[it].y; }
-        else vb[it] = B[(long long)(k0 + kk) * ldb + col0 + c];
-      }
+      if (col0 + c < N && k0 + kk < kend)
+        vb[it] = transB ? B[(long long)(col0 + c) * ldb + k0 + kk] : B[(long long)(k0 + kk) * ldb + col0 + c];
     }
   };
   auto lstore = [&](int buf) {
@@ -85,11 +83,12 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int M, int N, int K, const d
       int r, c, kk;
       a_coord(idx, r, kk);
       sA[buf][kk][0][r] = va[it].x;
-      sA[buf][kk][1][r] = va[it].y;
+      sA[buf][kk][1][r] = transA ? -va[it].y : va[it].y;
       b_coord(idx, c, kk);
+      const double by = transB ? -vb[it].y : vb[it].y;
       sX[buf][kk][0][c] = vb[it].x;
-      sX[buf][kk][1][c] = -vb[it].y;
-      sY[buf][kk][0][c] = vb[it].y;
+      sX[buf][kk][1][c] = -by;
+      sY[buf][kk][0][c] = by;
       sY[buf][kk][1][c] = vb[it].x;
     }
   };
