@@ -19,7 +19,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int GT = 64;    // output tile
 constexpr int GK = 8;     // complex k per stage
 
-__global__ __launch_bounds__(256) void zgemm_kernel(int M, int N, int K, const double2 *__restrict__ A, long long lda,
+__global__ __launch_bounds__(256, 3) void zgemm_kernel(int M, int N, int K, const double2 *__restrict__ A, long long lda,
                                                     int transA, const double2 *__restrict__ B, long long ldb,
                                                     int transB, double2 *__restrict__ C, long long ldc, double alpha,
                                                     double beta, int lower_only, int tri_k, int kchunk,
