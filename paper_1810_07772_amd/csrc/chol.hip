@@ -19,7 +19,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int GT = 64;    // output tile
 constexpr int GK = 8;     // complex k per stage
 
-__global__ __launch_bounds__(256, 3) void zgemm_kernel(int M, int N, int K, const double2 *__restrict__ A, long long lda,
+__global__ __launch_bounds__(256, 4) void zgemm_kernel(int M, int N, int K, const double2 *__restrict__ A, long long lda,
                                                     int transA, const double2 *__restrict__ B, long long ldb,
                                                     int transB, double2 *__restrict__ C, long long ldc, double alpha,
                                                     double beta, int lower_only, int tri_k, int kchunk,
@@ -34,8 +34,7 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(int M, int N, int K, cons
   if (lower_only && col0 >= row0 + GT) return;
   // two LDS stages: the global loads of stage k+1 are in flight in registers while stage k's MFMAs run
   __shared__ double sA[2][GK][2][GT];
-  __shared__ double sX[2][GK][2][GT];
-  __shared__ double sY[2][GK][2][GT];
+  __shared__ double sX[2][GK][2][GT];   // [Re B; -Im B]; the [Im B; Re B] operand is read from it
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
   f64x4 accR[2][2], accI[2][2];
@@ -88,8 +87,6 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(int M, int N, int K, cons
       const double by = transB ? -vb[it].y : vb[it].y;
       sX[buf][kk][0][c] = vb[it].x;
       sX[buf][kk][1][c] = -by;
-      sY[buf][kk][0][c] = by;
-      sY[buf][kk][1][c] = vb[it].x;
     }
   };
   int buf = 0;
@@ -106,7 +103,9 @@ __global__ __launch_bounds__(256, 3) void zgemm_kernel(int M, int N, int K, cons
       const int kk = 2 * s + (kl >> 1), comp = kl & 1;
       const double a0 = sA[buf][kk][comp][wr * 32 + li], a1 = sA[buf][kk][comp][wr * 32 + 16 + li];
       const double x0 = sX[buf][kk][comp][wc * 32 + li], x1 = sX[buf][kk][comp][wc * 32 + 16 + li];
-      const double y0 = sY[buf][kk][comp][wc * 32 + li], y1 = sY[buf][kk][comp][wc * 32 + 16 + li];
+      // Y = [Im B; Re B] = [-X_1; X_0]
+      const double ys0 = sX[buf][kk][comp ^ 1][wc * 32 + li], ys1 = sX[buf][kk][comp ^ 1][wc * 32 + 16 + li];
+      const double y0 = comp ? ys0 : -ys0, y1 = comp ? ys1 : -ys1;
       accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0, accR[0][0], 0, 0, 0);
       accI[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, y0, accI[0][0], 0, 0, 0);
       accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x1, accR[0][1], 0, 0, 0);
