@@ -159,15 +159,18 @@ __global__ __launch_bounds__(256) void herm_jacobi_kernel(const double2 *__restr
         if (tid == 0) { p = round; q = m - 1; }
         else { p = (round + tid) % (m - 1); q = (round - tid + (m - 1)) % (m - 1); }
         if (p > q) { const int t = p; p = q; q = t; }
+        // one reciprocal square root gives the phase and tau; c = 1/sqrt(1 + t^2) is another (three
+        // long-latency operations in this serial chain instead of seven)
         const double2 apq = A[p][q];
-        const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+        const double mag2 = apq.x * apq.x + apq.y * apq.y;
         double c = 1.0, s = 0.0;
         double2 ph = make_double2(1.0, 0.0);
-        if (mag > 0.0) {
-          ph = make_double2(apq.x / mag, apq.y / mag);
-          const double tau = (A[q][q].x - A[p][p].x) / (2.0 * mag);
+        if (mag2 > 0.0) {
+          const double inv_mag = rsqrt(mag2);
+          ph = make_double2(apq.x * inv_mag, apq.y * inv_mag);
+          const double tau = (A[q][q].x - A[p][p].x) * (0.5 * inv_mag);
           const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
+          c = rsqrt(1.0 + t * t);
           s = t * c;
         }
         rp[tid] = p; rq[tid] = q; rc[tid] = c; rs[tid] = s; rph[tid] = ph;
