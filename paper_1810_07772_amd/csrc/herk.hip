@@ -8,20 +8,22 @@
 // and the imaginary part is a real GEMM of X (rows) with Y = [b; -a] (columns).
 //
 // Work decomposition: one workgroup per lower-triangle tile (I, J) of the N_r x N_r output
-// (the paper's 2-D PMatrix tiles), 4 waves each owning a 64x64 quadrant.  The K loop walks
-// occupied bands v and chunks of KC unoccupied bands; for each chunk the workgroup loads
+// (the paper's 2-D PMatrix tiles), with 4 MFMA waves each owning a 64x64 quadrant.  The K loop
+// walks occupied bands v and chunks of unoccupied bands; for each chunk the workgroup loads
 // psi_c[chunk][I u J] (and psi_v[v][I u J]), forms only the f entries its tile needs (the
 // paper's local-f optimisation), and stages them in LDS (double buffered, one barrier per
-// chunk) so the loads of chunk i+1 overlap the MFMAs of chunk i.  The epilogue writes
-// the tile and, off the diagonal, its conjugate transpose.
+// stage) so the forming of stage i+1 overlaps the MFMAs of stage i.  The epilogue writes the
+// tile and, off the diagonal, its conjugate transpose.
 //
 // Variants:
 //  * FP32:  f in FP32 on v_mfma_f32_32x32x2f32.  Each occupied band's sum (nc pairs) is
 //    accumulated in fresh registers and folded into a running FP32 sum (two-level sum).
 //  * split BF16 / FP16: f = hi + lo (RNE), products hi*hi + hi*lo + lo*hi on
 //    v_mfma_f32_32x32x16_{bf16,f16}, FP32 accumulation.  The FP16 variant multiplies each
-//    band's f by 2^e_v (one exponent per occupied band) and folds the band's partial sum
-//    back with 2^-2e_v.
+//    band's f by 2^e_v (one exponent per occupied band) and undoes it exactly.  The default
+//    split kernels are wave-specialised (herk_split_ws_kernel): separate producer waves form
+//    and split f while the MFMA waves run, and the partial sums are added into P every
+//    32768 pairs.
 #include "gw_internal.h"
 
 namespace gwi {
