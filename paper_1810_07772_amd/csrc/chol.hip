@@ -353,6 +353,80 @@ hipError_t launch_fill_int(int *p, int value, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- block substitution of one panel of rows, X[p0:p1, :] from B[p0:p1, :] ----------------------------
+// The columns of B are independent, so a workgroup carries its SUB_CW columns through the panel's
+// 32-row steps in LDS: X_k = Linv_kk B_k, then B_i -= L_ik X_k for the panel's later row blocks.
+// One launch per panel replaces two small GEMMs per step.
+constexpr int CHOL_PW = 128;   // panel width of the factorisation and the substitution
+constexpr int SUB_CW = 32;     // columns per workgroup
+
+__global__ __launch_bounds__(256) void subst_panel_kernel(const double2 *__restrict__ B, const double2 *__restrict__ L,
+                                                          const double2 *__restrict__ linv_all,
+                                                          double2 *__restrict__ X, int n, int p0, int p1) {
+  __shared__ double2 sB[CHOL_PW][SUB_CW + 1];
+  __shared__ double2 sM[NB][NB + 1];   // Linv_kk, then one L_ik block at a time
+  constexpr int PER = NB * SUB_CW / 256;
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * SUB_CW;
+  const int rows = p1 - p0;
+  for (int idx = tid; idx < CHOL_PW * SUB_CW; idx += 256) {
+    const int i = idx / SUB_CW, c = idx % SUB_CW;
+    sB[i][c] = (i < rows && c0 + c < n) ? B[(size_t)(p0 + i) * n + c0 + c] : make_double2(0.0, 0.0);
+  }
+  for (int k0 = p0; k0 < p1; k0 += NB) {
+    const int nb = min(NB, n - k0), kr = k0 - p0;
+    for (int idx = tid; idx < NB * NB; idx += 256) sM[idx / NB][idx % NB] = linv_all[(size_t)(k0 / NB) * NB * NB + idx];
+    __syncthreads();
+    // X_k = Linv_kk B_k (Linv lower triangular)
+    double2 xv[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int idx = tid + 256 * t, i = idx / SUB_CW, c = idx % SUB_CW;
+      double re = 0.0, im = 0.0;
+      for (int m = 0; m <= i; ++m) {
+        const double2 u = sM[i][m], v = sB[kr + m][c];
+        re += u.x * v.x - u.y * v.y;
+        im += u.x * v.y + u.y * v.x;
+      }
+      xv[t] = make_double2(re, im);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int idx = tid + 256 * t, i = idx / SUB_CW, c = idx % SUB_CW;
+      if (i < nb) {
+        sB[kr + i][c] = xv[t];
+        if (c0 + c < n) X[(size_t)(k0 + i) * n + c0 + c] = xv[t];
+      }
+    }
+    // the panel's later row blocks: B_i -= L_ik X_k
+    for (int j0 = k0 + NB; j0 < p1; j0 += NB) {
+      const int jn = min(NB, p1 - j0), jr = j0 - p0;
+      __syncthreads();
+      for (int idx = tid; idx < NB * NB; idx += 256) {
+        const int i = idx / NB, m = idx % NB;
+        sM[i][m] = (i < jn && m < nb) ? L[(size_t)(j0 + i) * n + k0 + m] : make_double2(0.0, 0.0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < PER; ++t) {
+        const int idx = tid + 256 * t, i = idx / SUB_CW, c = idx % SUB_CW;
+        if (i < jn) {
+          double re = 0.0, im = 0.0;
+          for (int m = 0; m < nb; ++m) {
+            const double2 u = sM[i][m], v = sB[kr + m][c];
+            re += u.x * v.x - u.y * v.y;
+            im += u.x * v.y + u.y * v.x;
+          }
+          sB[jr + i][c].x -= re;
+          sB[jr + i][c].y -= im;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 size_t chol_small_bytes(int n) {
   const int nblk = (n + NB - 1) / NB;
   return (size_t)nblk * NB * NB * sizeof(double2);
@@ -370,7 +444,7 @@ hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small
   // Panels of PW columns: inside a panel each NB-wide step updates only the panel's columns; one
   // K = PW product then updates everything right of (factorisation) or below (substitution) the panel,
   // so the large trailing matrix is read and written once per panel instead of once per NB step.
-  constexpr int PW = 128;   // 128, 256 and 512 measured alike; 32 (no panels) 5% slower at N = 4067
+  constexpr int PW = CHOL_PW;   // 128, 256 and 512 measured alike; 32 (no panels) 5% slower at N = 4067
   // 1. factor a = L L^H
   for (int p0 = 0; p0 < n; p0 += PW) {
     const int p1 = min(n, p0 + PW);
@@ -404,17 +478,10 @@ hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small
   GW_TRY(hipGetLastError());
   for (int p0 = 0; p0 < n; p0 += PW) {
     const int p1 = min(n, p0 + PW);
-    for (int k0 = p0; k0 < p1; k0 += NB) {
-      const int kb = k0 / NB, nb = min(NB, n - k0), ncol = k0 + nb;
-      const double2 *linv = small + (size_t)kb * NB * NB;
-      // X_k = Linv_kk B_k (block row k, columns < k0+nb)
-      GW_TRY(zgemm(nb, ncol, nb, linv, NB, 0, a + (size_t)k0 * n, n, 0, x + (size_t)k0 * n, n, 1.0, 0.0, 0, 0, s));
-      // B_i -= L_ik X_k for the block rows below inside the panel
-      const int wrows = p1 - (k0 + nb);
-      if (wrows > 0)
-        GW_TRY(zgemm(wrows, ncol, nb, l + (size_t)(k0 + nb) * n + k0, n, 0, x + (size_t)k0 * n, n, 0,
-                     a + (size_t)(k0 + nb) * n, n, -1.0, 1.0, 0, 0, s));
-    }
+    // the panel's rows of X (columns < p1; X is zero beyond), all 32-row steps in one launch
+    hipLaunchKernelGGL(subst_panel_kernel, dim3((p1 + SUB_CW - 1) / SUB_CW), dim3(256), 0, s, a, l, small, x, n, p0,
+                       p1);
+    GW_TRY(hipGetLastError());
     // below the panel: B[p1:, :p1] -= L[p1:, p0:p1] X[p0:p1, :p1]
     const int rest = n - p1;
     if (rest > 0)
