@@ -22,7 +22,8 @@
  * - Energies are float64 in Hartree.  Every E_c - E_v must be > 0.
  * - The G-sphere is an ordered host list of Miller triples g_miller[ng][3]
  *   (int32) with |m_d| < n_d/2 and no duplicates; outputs indexed by g follow
- *   that order.  q is in crystal units; the cell is cubic with side a_bohr.
+ *   that order.  q (host, [3], finite; GW_E_INVAL otherwise) is in crystal units;
+ *   the cell is cubic with side a_bohr.
  * - Where |q+G| < 1e-10 * 2pi/a, sqrt(V) is taken as 0 and eps(g,g) is set to
  *   the caller's `head` value (the wings become 0).
  * - Ownership: the caller owns every buffer it passes and the library never

@@ -146,6 +146,12 @@ int check_sphere(gw_ctx *ctx, gw_grid g, const int *miller, int ng) {
   return GW_OK;
 }
 
+int check_q(gw_ctx *ctx, const double *q) {
+  GW_CHECK(ctx, q != nullptr, "q must not be NULL");
+  GW_CHECK(ctx, std::isfinite(q[0]) && std::isfinite(q[1]) && std::isfinite(q[2]), "q must be finite");
+  return GW_OK;
+}
+
 int check_opts(gw_ctx *ctx, const gw_opts *o) {
   GW_CHECK(ctx, o->precision == GW_FP32 || o->precision == GW_SPLIT_BF16 || o->precision == GW_SPLIT_FP16_SCALED,
            "unknown precision %d", o->precision);
@@ -526,8 +532,7 @@ int gw_polarizability(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const gw_c32 *
   GW_CHECK(ctx, nrl <= (1 << 24), "grid too large");
   const int nr = (int)nrl;
   GW_STATUS(check_bands(ctx, psi_occ, nv, psi_unocc, nc, nr));
-  GW_CHECK(ctx, q != nullptr, "q must not be NULL");
-  GW_CHECK(ctx, std::isfinite(q[0]) && std::isfinite(q[1]) && std::isfinite(q[2]), "q must be finite");
+  GW_STATUS(check_q(ctx, q));
   GW_CHECK(ctx, p_gg != nullptr, "p_gg must not be NULL");
   GW_CHECK(ctx, !(o.accumulate && !p_rr), "accumulate needs the caller's p_rr buffer");
   GW_STATUS(check_opts(ctx, &o));
@@ -551,7 +556,7 @@ int gw_epsilon(gw_ctx *ctx, const gw_c32 *p_gg, int ng, gw_grid grid, const doub
                double head, gw_c64 *eps_out, void *stream) {
   GW_STATUS(begin(ctx));
   GW_CHECK(ctx, p_gg && eps_out, "p_gg and eps_out must not be NULL");
-  GW_CHECK(ctx, q != nullptr, "q must not be NULL");
+  GW_STATUS(check_q(ctx, q));
   GW_STATUS(check_grid(ctx, grid));
   GW_STATUS(check_sphere(ctx, grid, g_miller, ng));
   if (std::isnan(head)) head = 1.0;
@@ -564,7 +569,7 @@ int gw_eps_inverse(gw_ctx *ctx, const gw_c32 *p_gg, int ng, gw_grid grid, const 
                    double head, gw_c64 *eps_inv, void *stream) {
   GW_STATUS(begin(ctx));
   GW_CHECK(ctx, p_gg && eps_inv, "p_gg and eps_inv must not be NULL");
-  GW_CHECK(ctx, q != nullptr, "q must not be NULL");
+  GW_STATUS(check_q(ctx, q));
   GW_STATUS(check_grid(ctx, grid));
   GW_STATUS(check_sphere(ctx, grid, g_miller, ng));
   if (std::isnan(head)) head = 1.0;
@@ -634,7 +639,7 @@ int gw_eps_inverse_newton(gw_ctx *ctx, const gw_c32 *p_gg, int ng, gw_grid grid,
                           void *stream) {
   GW_STATUS(begin(ctx));
   GW_CHECK(ctx, p_gg && eps_inv && iterations, "p_gg, eps_inv and iterations must not be NULL");
-  GW_CHECK(ctx, q != nullptr, "q must not be NULL");
+  GW_STATUS(check_q(ctx, q));
   GW_STATUS(check_grid(ctx, grid));
   GW_STATUS(check_sphere(ctx, grid, g_miller, ng));
   if (std::isnan(head)) head = 1.0;

@@ -48,6 +48,7 @@ int gw_tail_features(gw_ctx *ctx, const gw_c32 *p_gg, int ng, gw_grid grid, cons
                      int nc, double e_max, float *feat, void *stream) {
   GWX_STATUS(api_begin(ctx));
   GWX_CHECK(ctx, p_gg && q && feat, "p_gg, q and feat must not be NULL");
+  GWX_CHECK(ctx, std::isfinite(q[0]) && std::isfinite(q[1]) && std::isfinite(q[2]), "q must be finite");
   GWX_CHECK(ctx, nc > 0 && std::isfinite(e_max), "nc must be positive and e_max finite");
   GWX_STATUS(api_check_grid(ctx, grid));
   GWX_STATUS(api_check_sphere(ctx, grid, g_miller, ng));

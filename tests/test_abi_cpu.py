@@ -132,6 +132,11 @@ def test_dry_run_other_entry_points(gw):
     assert lib.gw_epsilon(h, vp(), len(m), grid, pq, pm, 1.0, vp(), None) == 0
     assert lib.gw_epsilon(h, vp(), len(m), grid, pq, pm, -2.0, vp(), None) == 1
     assert lib.gw_eps_inverse(h, vp(), len(m), grid, pq, pm, float("nan"), vp(), None) == 0
+    # a non-finite q is rejected by every entry point that builds the Coulomb factor
+    qn, pqn = f64([0.0, np.nan, 0.0])
+    assert lib.gw_epsilon(h, vp(), len(m), grid, pqn, pm, 1.0, vp(), None) == 1
+    assert lib.gw_eps_inverse(h, vp(), len(m), grid, pqn, pm, 1.0, vp(), None) == 1
+    assert lib.gw_eps_inverse(h, vp(), len(m), grid, None, pm, 1.0, vp(), None) == 1
     assert lib.gw_hpd_inverse(h, vp(), 0, vp(), None) == 1
     assert lib.gw_hpd_inverse(h, vp(), 10, vp(), None) == 0
     assert lib.gw_create(None, 0, 0) == 1
@@ -178,6 +183,8 @@ def test_dry_run_other_entry_points(gw):
     assert lib.gw_eps_inverse_newton(h, vp(), len(m), grid, pq, pm, 1.0, 1e-11, 50, vp(), C.byref(its), None,
                                      None) == 0
     assert lib.gw_eps_inverse_newton(h, vp(), len(m), grid, pq, pm, 1.0, float("nan"), 50, vp(), C.byref(its), None,
+                                     None) == 1
+    assert lib.gw_eps_inverse_newton(h, vp(), len(m), grid, pqn, pm, 1.0, 1e-11, 50, vp(), C.byref(its), None,
                                      None) == 1
 
 
