@@ -200,7 +200,9 @@ __global__ __launch_bounds__(FFT_THREADS) void fft_gather_pass_kernel(const floa
 // The gather pass along the last axis (U = 1) with its output transposed on the way: 64 batch columns
 // (bands) and 4 consecutive lines per workgroup; each thread transforms one line into an LDS tile, and
 // the workgroup then writes each band's 4 N consecutive outputs to its own row, out[b][o N + k].  This
-// replaces a [grid][band] intermediate and a separate transpose of it.
+// replaces a [grid][band] intermediate and a separate transpose of it.  Each wave holds one line, so
+// its map row is read through the scalar cache; grid.x runs over line groups, so the workgroups in
+// flight write a few bands' rows at a time rather than a short run of every band's row.
 constexpr int GT_BANDS = 64, GT_LINES = FFT_THREADS / GT_BANDS;
 template <int N, int SIGN>
 __global__ __launch_bounds__(FFT_THREADS) void fft_gather_pass_t_kernel(const float2 *__restrict__ in,
@@ -208,9 +210,10 @@ __global__ __launch_bounds__(FFT_THREADS) void fft_gather_pass_t_kernel(const fl
                                                                          long long ld_in, long long ld_out,
                                                                          const int *__restrict__ map, float scale) {
   __shared__ float2 tile[GT_LINES * N][GT_BANDS + 1];
-  const int tb = threadIdx.x % GT_BANDS, l = threadIdx.x / GT_BANDS;
-  const int b0 = blockIdx.x * GT_BANDS, b = b0 + tb;
-  const int o0 = blockIdx.y * GT_LINES, o = o0 + l;
+  static_assert(GT_BANDS == 64, "one line per wave");
+  const int tb = threadIdx.x % GT_BANDS, l = __builtin_amdgcn_readfirstlane(threadIdx.x / GT_BANDS);
+  const int o0 = blockIdx.x * GT_LINES, o = o0 + l;
+  const int b0 = blockIdx.y * GT_BANDS, b = b0 + tb;
   if (o < O) {
     const int *mrow = map + (size_t)o * N;
     float2 x[N], X[N];
@@ -231,10 +234,21 @@ __global__ __launch_bounds__(FFT_THREADS) void fft_gather_pass_t_kernel(const fl
   }
   __syncthreads();
   const int nl = min(GT_LINES, O - o0), nb = min(GT_BANDS, B - b0);
-  const int run = nl * N;                       // consecutive outputs per band in this block
-  for (int v = threadIdx.x; v < nb * run; v += FFT_THREADS) {
-    const int band = v / run, kk = v - band * run;
-    out[(long long)(b0 + band) * ld_out + (long long)o0 * N + kk] = tile[kk][band];
+  float2 *ob = out + (long long)b0 * ld_out + (long long)o0 * N;
+  if (nl == GT_LINES && nb == GT_BANDS) {
+    // full block: GT_LINES * N consecutive outputs per band, N stores per thread
+    constexpr int RUN = GT_LINES * N;
+#pragma unroll 4
+    for (int it = 0; it < GT_BANDS * RUN / FFT_THREADS; ++it) {
+      const int v = (int)threadIdx.x + it * FFT_THREADS, band = v / RUN, kk = v - band * RUN;
+      ob[(long long)band * ld_out + kk] = tile[kk][band];
+    }
+  } else {
+    const int run = nl * N;                     // consecutive outputs per band in this block
+    for (int v = threadIdx.x; v < nb * run; v += FFT_THREADS) {
+      const int band = v / run, kk = v - band * run;
+      ob[(long long)band * ld_out + kk] = tile[kk][band];
+    }
   }
 }
 
@@ -295,7 +309,7 @@ hipError_t launch_fft_gather_pass(int n, int sign, const float2 *in, float2 *out
 
 hipError_t launch_fft_gather_pass_t(int n, int sign, const float2 *in, float2 *out, int O, int B, long long ld_in,
                                     long long ld_out, const int *map, float scale, hipStream_t s) {
-  dim3 grid((B + GT_BANDS - 1) / GT_BANDS, (O + GT_LINES - 1) / GT_LINES), block(FFT_THREADS);
+  dim3 grid((O + GT_LINES - 1) / GT_LINES, (B + GT_BANDS - 1) / GT_BANDS), block(FFT_THREADS);
   if (grid.y > 65535) return hipErrorInvalidValue;
   switch (n) {
 #define GW_CASE(n_)                                                                                             \

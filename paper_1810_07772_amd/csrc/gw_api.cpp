@@ -248,18 +248,43 @@ hipError_t enqueue_sphere_transform(const SpherePlan &p, const SphereBuffers &b,
   return launch_transpose_c64(b.q, p_gg, ng, ng, ng, ng, s);
 }
 
+// The plan's sizes and the device addresses of its maps in `map_slot`.  A call with the grid, Miller
+// list and stream of the slot's previous upload reuses the device maps: no host rebuild, and no
+// pageable copy that would stall the stream.  `p` receives the plan's sizes (its host maps stay empty).
 int upload_plan(gw_ctx *ctx, gw_grid g, const int *miller, int ng, int map_slot, SpherePlan &p, int **dA, int **dB,
                 int **dC, hipStream_t s) {
-  build_sphere_plan(g, miller, ng, p);
-  const size_t nA = p.mapA.size(), nB = p.mapB.size(), nC = p.mapC.size();
+  std::unique_ptr<PlanCacheEntry> &e = ctx->plans[map_slot];
+  const size_t nm = (size_t)ng * 3;
+  const bool same = e && e->g.n1 == g.n1 && e->g.n2 == g.n2 && e->g.n3 == g.n3 && e->miller.size() == nm &&
+                    std::equal(miller, miller + nm, e->miller.begin()) && e->stream == (void *)s;
+  if (!same) {
+    e.reset(new (std::nothrow) PlanCacheEntry());
+    if (!e) {
+      set_err(ctx, "out of host memory for the sphere plan");
+      return GW_E_NOMEM;
+    }
+    build_sphere_plan(g, miller, ng, e->plan);
+    e->g = g;
+    e->miller.assign(miller, miller + nm);
+    e->stream = (void *)s;
+  }
+  const SpherePlan &pl = e->plan;
+  const size_t nA = pl.mapA.size(), nB = pl.mapB.size(), nC = pl.mapC.size();
   void *maps;
   GW_STATUS(ws_get(ctx, map_slot, (nA + nB + nC) * sizeof(int), &maps, s));
   *dA = (int *)maps;
   *dB = *dA + nA;
   *dC = *dB + nB;
-  GW_HIP(ctx, hipMemcpyAsync(*dA, p.mapA.data(), nA * sizeof(int), hipMemcpyHostToDevice, s));
-  GW_HIP(ctx, hipMemcpyAsync(*dB, p.mapB.data(), nB * sizeof(int), hipMemcpyHostToDevice, s));
-  GW_HIP(ctx, hipMemcpyAsync(*dC, p.mapC.data(), nC * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!same || maps != e->maps) {
+    e->maps = nullptr;   // not valid until every copy below is queued
+    GW_HIP(ctx, hipMemcpyAsync(*dA, pl.mapA.data(), nA * sizeof(int), hipMemcpyHostToDevice, s));
+    GW_HIP(ctx, hipMemcpyAsync(*dB, pl.mapB.data(), nB * sizeof(int), hipMemcpyHostToDevice, s));
+    GW_HIP(ctx, hipMemcpyAsync(*dC, pl.mapC.data(), nC * sizeof(int), hipMemcpyHostToDevice, s));
+    e->maps = maps;
+  }
+  p.n1 = pl.n1; p.n2 = pl.n2; p.n3 = pl.n3; p.ng = pl.ng;
+  p.m3count = pl.m3count; p.npair = pl.npair;
+  p.bc = pl.bc; p.a1_elems = pl.a1_elems; p.a2_elems = pl.a2_elems;
   return GW_OK;
 }
 
@@ -499,7 +524,6 @@ int gw_orbitals_to_grid(gw_ctx *ctx, const gw_c32 *coeff, int nb, int npw, gw_gr
   // band chunk: an intermediate of [nr][w] elements would stay near 1 GiB
   const int w = (int)std::min<long long>(nb, std::max<long long>(64, (1LL << 27) / nr));
   const size_t rows1 = (size_t)p.n1 * p.n2 * p.m3count, rows2 = (size_t)p.n1 * p.npair;
-  GW_CHECK(ctx, ((long long)p.n1 * p.n2 + 3) / 4 <= 65535, "grid too large for the orbital transform");
   void *ct, *a1, *a2;
   GW_STATUS(ws_get(ctx, WS_ORB_T, (size_t)npw * w * sizeof(float2), &ct, s));
   GW_STATUS(ws_get(ctx, WS_ORB_A1, rows1 * w * sizeof(float2), &a1, s));

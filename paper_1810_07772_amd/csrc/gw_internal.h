@@ -7,10 +7,15 @@
 #include <cstdio>
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/gw.h"
+
+namespace gwi {
+struct PlanCacheEntry;
+}
 
 struct gw_ctx {
   int device = -1;            // -1: dry-run context (argument checks only)
@@ -24,6 +29,8 @@ struct gw_ctx {
   std::map<std::string, int> tuned;   // autotuned update tiles, keyed by arch and shape
   bool tune_loaded = false;           // the autotune cache file has been read
   std::string arch;                   // device architecture name (cached)
+  // the sphere plan last uploaded into each map slot, reused while grid, Miller list and stream match
+  std::map<int, std::unique_ptr<gwi::PlanCacheEntry>> plans;
 };
 
 namespace gwi {
@@ -176,6 +183,13 @@ struct SpherePlan {
   size_t a1_elems = 0, a2_elems = 0;
 };
 void build_sphere_plan(gw_grid g, const int *miller, int ng, SpherePlan &p);
+struct PlanCacheEntry {
+  gw_grid g{};
+  std::vector<int> miller;   // [ng][3], the list the plan was built from
+  void *stream = nullptr;    // stream the maps were uploaded on
+  void *maps = nullptr;      // device copy of the maps (the slot's buffer at upload)
+  SpherePlan plan;
+};
 struct SphereBuffers {
   float2 *a1, *a2, *ph, *pht, *q;  // pass intermediates, P^ [ng][nr], its transpose, Q [ng][ng]
   const int *dA, *dB, *dC;         // device copies of the plan's maps

@@ -96,3 +96,40 @@ def test_feeds_the_polarizability_build(gw):
     e = orc.rel_f(p_dev, ref)
     print(f"P~ from device orbitals: rel_F {e:.2e}")
     assert e < 1e-5
+
+
+def test_plan_reuse_follows_the_miller_list(gw):
+    """Repeated calls reuse the uploaded sphere plan only for the same grid, Miller list and stream:
+    the same sphere in another order (same size, same grid) must give outputs in that order, also
+    after switching back, on a second stream, and for the P transform's own plan."""
+    n = (10, 10, 10)
+    mp = gs.sphere(n, r2=9.0)
+    rng = np.random.default_rng(10)
+    perm = rng.permutation(len(mp))
+    c = (rng.standard_normal((20, len(mp))) + 1j * rng.standard_normal((20, len(mp)))).astype(np.complex64)
+    ref = orc.orbitals_on_grid(c.astype(np.complex128), mp, n)
+    side = torch.cuda.Stream()
+    runs = [(mp, c, None), (mp, c, None), (mp[perm], c[:, perm], None), (mp, c, None),
+            (mp[perm], c[:, perm], side), (mp[perm], c[:, perm], None)]
+    for i, (m, cc, st) in enumerate(runs):
+        if st is None:
+            psi = gw.orbitals_to_grid(c64(cc), n, m)
+        else:
+            with torch.cuda.stream(st):
+                psi = gw.orbitals_to_grid(c64(cc), n, m)
+            st.synchronize()
+        e = orc.rel_f(psi.cpu().numpy(), ref)
+        print(f"orbitals call {i}: rel_F {e:.2e}")
+        assert e < 1e-6
+    # the P(r,r') -> P~(g,g') transform with the sphere in two orders
+    n6 = (6, 6, 6)
+    ms = gs.sphere(n6, r2=4.0)
+    nr = 216
+    p = (rng.standard_normal((nr, nr)) + 1j * rng.standard_normal((nr, nr))).astype(np.complex64)
+    ps = rng.permutation(len(ms))
+    for m in (ms, ms[ps], ms):
+        got = gw.sphere_transform(c64(p), n6, m).cpu().numpy()
+        want = orc.to_sphere(p.astype(np.complex128), n6, m)
+        e = orc.rel_f(got, want)
+        print(f"sphere transform, {len(m)} G: rel_F {e:.2e}")
+        assert e < 1e-5
