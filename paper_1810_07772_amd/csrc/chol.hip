@@ -212,9 +212,20 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
                                                          int *__restrict__ pivot) {
   __shared__ double2 a[NB][NB + 1];
   __shared__ double2 x[NB][NB + 1];
+  __shared__ double2 pa[64][NB + 1];
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int nb = min(NB, n - k0);
+  // this workgroup's 64 panel rows below the block, loaded now so that their latency overlaps the
+  // factorisation: thread (pib, pj) holds A[r0 + pib + 8t][k0 + pj]
+  const int r0 = k0 + nb + (int)blockIdx.x * 64;
+  const int pj = tid % NB, pib = tid / NB;
+  double2 pv[64 * NB / 256];
+#pragma unroll
+  for (int t = 0; t < 64 * NB / 256; ++t) {
+    const int r = r0 + pib + 8 * t;
+    pv[t] = (r < n && pj < nb) ? A[(size_t)r * n + k0 + pj] : make_double2(0.0, 0.0);
+  }
   if (tid == 0) bad = 0;
   for (int idx = tid; idx < NB * NB; idx += 256) {
     const int i = idx / NB, j = idx % NB;
@@ -226,21 +237,34 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
   __syncthreads();
   // unblocked right-looking Cholesky on the lower triangle, with unscaled columns: step j subtracts
   // s_j s_j^H / d_j (d_j the pivot) from the trailing lower triangle, which needs one barrier per
-  // step; column j is final after step j and is scaled to L in one pass at the end.
-  for (int j = 0; j < NB; ++j) {
-    __syncthreads();
-    double d = a[j][j].x;
-    if (!(d > 0.0) || !isfinite(d)) {
-      if (tid == 0 && j < nb && bad == 0) bad = k0 + j + 1;
-      d = 1.0;
-    }
-    const double dinv = 1.0 / d;
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-      const int i = idx / NB, m = idx % NB;
-      if (m > j && m <= i) {
-        const double2 p = a[i][j], q = a[m][j];
-        a[i][m].x -= (p.x * q.x + p.y * q.y) * dinv;
-        a[i][m].y -= (p.y * q.x - p.x * q.y) * dinv;
+  // step; column j is final after step j and is scaled to L in one pass at the end.  A thread owns
+  // column m = tid % NB of rows tid / NB + 8t; step j writes only columns m > j, so every read of the
+  // step (column j and the thread's four entries) is issued before its first write.
+  {
+    const int m = tid % NB, ib = tid / NB;
+    for (int j = 0; j < NB; ++j) {
+      __syncthreads();
+      double d = a[j][j].x;
+      if (!(d > 0.0) || !isfinite(d)) {
+        if (tid == 0 && j < nb && bad == 0) bad = k0 + j + 1;
+        d = 1.0;
+      }
+      const double dinv = 1.0 / d;
+      const double2 q = a[m][j];
+      double2 p[NB * NB / 256], c[NB * NB / 256];
+#pragma unroll
+      for (int t = 0; t < NB * NB / 256; ++t) {
+        p[t] = a[ib + 8 * t][j];
+        c[t] = a[ib + 8 * t][m];
+      }
+#pragma unroll
+      for (int t = 0; t < NB * NB / 256; ++t) {
+        const int i = ib + 8 * t;
+        if (m > j && m <= i) {
+          c[t].x -= (p[t].x * q.x + p[t].y * q.y) * dinv;
+          c[t].y -= (p[t].y * q.x - p[t].x * q.y) * dinv;
+          a[i][m] = c[t];
+        }
       }
     }
   }
@@ -296,26 +320,30 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
     if (tid == 0 && bad != 0 && *pivot == 0) *pivot = bad;
   }
   // panel below the block, 64 rows per workgroup (every workgroup factored the block above for itself):
-  // L[r][k0 + j] = sum_{k <= j} A[r][k0 + k] conj(Linv[j][k])
-  const int r0 = k0 + nb + (int)blockIdx.x * 64;
+  // L[r][k0 + j] = sum_{k <= j} A[r][k0 + k] conj(Linv[j][k]).  Linv is lower triangular with its upper
+  // part stored as zeros, so the k loop runs to NB for every thread: no divergence, and eight
+  // independent accumulators per thread (rows pib + 8t of column pj).
   if (r0 >= n) return;
-  __shared__ double2 pa[64][NB + 1];
-  for (int idx = tid; idx < 64 * NB; idx += 256) {
-    const int i = idx / NB, k = idx % NB;
-    pa[i][k] = (r0 + i < n && k < nb) ? A[(size_t)(r0 + i) * n + k0 + k] : make_double2(0.0, 0.0);
-  }
+#pragma unroll
+  for (int t = 0; t < 64 * NB / 256; ++t) pa[pib + 8 * t][pj] = pv[t];
   __syncthreads();
-  for (int idx = tid; idx < 64 * NB; idx += 256) {
-    const int i = idx / NB, j = idx % NB;
-    if (r0 + i < n && j < nb) {
-      double sr = 0.0, si = 0.0;
-      for (int k = 0; k <= j; ++k) {
-        const double2 av = pa[i][k], v = x[j][k];
-        sr += av.x * v.x + av.y * v.y;
-        si += av.y * v.x - av.x * v.y;
-      }
-      L[(size_t)(r0 + i) * n + k0 + j] = make_double2(sr, si);
+  double2 acc[64 * NB / 256];
+#pragma unroll
+  for (int t = 0; t < 64 * NB / 256; ++t) acc[t] = make_double2(0.0, 0.0);
+#pragma unroll 4
+  for (int k = 0; k < NB; ++k) {
+    const double2 v = x[pj][k];
+#pragma unroll
+    for (int t = 0; t < 64 * NB / 256; ++t) {
+      const double2 av = pa[pib + 8 * t][k];
+      acc[t].x += av.x * v.x + av.y * v.y;
+      acc[t].y += av.y * v.x - av.x * v.y;
     }
+  }
+#pragma unroll
+  for (int t = 0; t < 64 * NB / 256; ++t) {
+    const int r = r0 + pib + 8 * t;
+    if (r < n && pj < nb) L[(size_t)r * n + k0 + pj] = acc[t];
   }
 }
 
