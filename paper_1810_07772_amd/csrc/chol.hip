@@ -287,15 +287,21 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
   __syncthreads();
   // inverse of the lower-triangular factor by forward substitution on each unit vector, L x = e_col:
   // eight lanes per column split the dot product over m and reduce it with shuffles; a column's eight
-  // lanes sit in one wave, so the rows of one column need no workgroup barrier between them
+  // lanes sit in one wave, so the rows of one column need no workgroup barrier between them.  Lane
+  // `part` takes m = part + 8s for all four s with m < i: a fixed trip count whose loads issue together
+  // (x[m][col] is already zero for m < col, so starting below col adds only zeros).
   {
     const int col = tid >> 3, part = tid & 7;
     for (int i = 0; i < NB; ++i) {
       double sr = 0.0, si = 0.0;
-      for (int m = col + part; m < i; m += 8) {
+#pragma unroll
+      for (int s4 = 0; s4 < NB / 8; ++s4) {
+        const int m = part + 8 * s4;
         const double2 l = a[i][m], v = x[m][col];
-        sr += l.x * v.x - l.y * v.y;
-        si += l.x * v.y + l.y * v.x;
+        if (m < i) {
+          sr += l.x * v.x - l.y * v.y;
+          si += l.x * v.y + l.y * v.x;
+        }
       }
       for (int off = 4; off > 0; off >>= 1) {
         sr += __shfl_xor(sr, off, 8);
@@ -405,18 +411,21 @@ __global__ __launch_bounds__(256) void subst_panel_kernel(const double2 *__restr
     const int nb = min(NB, n - k0), kr = k0 - p0;
     for (int idx = tid; idx < NB * NB; idx += 256) sM[idx / NB][idx % NB] = linv_all[(size_t)(k0 / NB) * NB * NB + idx];
     __syncthreads();
-    // X_k = Linv_kk B_k (Linv lower triangular)
+    // X_k = Linv_kk B_k.  Linv_kk is stored with zeros above its diagonal, so m runs over the whole
+    // block for every thread: thread (i = ib + 8t, c) keeps PER independent sums.
+    const int ib = tid / SUB_CW, c = tid % SUB_CW;
     double2 xv[PER];
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      const int idx = tid + 256 * t, i = idx / SUB_CW, c = idx % SUB_CW;
-      double re = 0.0, im = 0.0;
-      for (int m = 0; m <= i; ++m) {
-        const double2 u = sM[i][m], v = sB[kr + m][c];
-        re += u.x * v.x - u.y * v.y;
-        im += u.x * v.y + u.y * v.x;
+    for (int t = 0; t < PER; ++t) xv[t] = make_double2(0.0, 0.0);
+#pragma unroll 4
+    for (int m = 0; m < NB; ++m) {
+      const double2 v = sB[kr + m][c];
+#pragma unroll
+      for (int t = 0; t < PER; ++t) {
+        const double2 u = sM[ib + 8 * t][m];
+        xv[t].x += u.x * v.x - u.y * v.y;
+        xv[t].y += u.x * v.y + u.y * v.x;
       }
-      xv[t] = make_double2(re, im);
     }
     __syncthreads();
 #pragma unroll
@@ -436,18 +445,26 @@ __global__ __launch_bounds__(256) void subst_panel_kernel(const double2 *__restr
         sM[i][m] = (i < jn && m < nb) ? L[(size_t)(j0 + i) * n + k0 + m] : make_double2(0.0, 0.0);
       }
       __syncthreads();
+      // sM is zero for m >= nb, so m runs over the whole block here too
+      double2 acc[PER];
+#pragma unroll
+      for (int t = 0; t < PER; ++t) acc[t] = make_double2(0.0, 0.0);
+#pragma unroll 4
+      for (int m = 0; m < NB; ++m) {
+        const double2 v = sB[kr + m][c];
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+          const double2 u = sM[ib + 8 * t][m];
+          acc[t].x += u.x * v.x - u.y * v.y;
+          acc[t].y += u.x * v.y + u.y * v.x;
+        }
+      }
 #pragma unroll
       for (int t = 0; t < PER; ++t) {
-        const int idx = tid + 256 * t, i = idx / SUB_CW, c = idx % SUB_CW;
+        const int i = ib + 8 * t;
         if (i < jn) {
-          double re = 0.0, im = 0.0;
-          for (int m = 0; m < nb; ++m) {
-            const double2 u = sM[i][m], v = sB[kr + m][c];
-            re += u.x * v.x - u.y * v.y;
-            im += u.x * v.y + u.y * v.x;
-          }
-          sB[jr + i][c].x -= re;
-          sB[jr + i][c].y -= im;
+          sB[jr + i][c].x -= acc[t].x;
+          sB[jr + i][c].y -= acc[t].y;
         }
       }
     }
