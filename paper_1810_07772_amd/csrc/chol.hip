@@ -24,14 +24,28 @@ __global__ __launch_bounds__(256, 4) void zgemm_kernel(int M, int N, int K, cons
                                                     int transB, double2 *__restrict__ C, long long ldc, double alpha,
                                                     double beta, int lower_only, int tri_k, int kchunk,
                                                     long long cz_stride) {
-  const int row0 = blockIdx.y * GT, col0 = blockIdx.x * GT;
+  // lower_only == 2: a square product over a one-dimensional grid of its lower tiles only, numbered row
+  // by row (t = r (r + 1) / 2 + c), so consecutive workgroups, which the dispatcher deals out to the XCDs
+  // in turn, carry equal work and no workgroup is launched for an upper tile
+  int row0, col0;
+  if (lower_only == 2) {
+    const int t = blockIdx.x;
+    int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    while (r * (r + 1) / 2 > t) --r;
+    row0 = r * GT;
+    col0 = (t - r * (r + 1) / 2) * GT;
+  } else {
+    row0 = blockIdx.y * GT;
+    col0 = blockIdx.x * GT;
+  }
   // split K: workgroup z takes k in [z kchunk, (z+1) kchunk) and writes its own partial C
   int kend = K;
   if (kchunk > 0) {
     C += blockIdx.z * cz_stride;
     kend = min(K, (int)(blockIdx.z + 1) * kchunk);
   }
-  if (lower_only && col0 >= row0 + GT) return;
+  if (lower_only == 1 && col0 >= row0 + GT) return;
   // two LDS stages: the global loads of stage k+1 are in flight in registers while stage k's MFMAs run
   __shared__ double sA[2][GK][2][GT];
   __shared__ double sX[2][GK][2][GT];   // [Re B; -Im B]; the [Im B; Re B] operand is read from it
@@ -141,6 +155,12 @@ static hipError_t zgemm(int M, int N, int K, const double2 *A, long long lda, in
                         long long ldb, int transB, double2 *C, long long ldc, double alpha, double beta,
                         int lower_only, int tri_k, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (lower_only && M == N) {
+    const long long nt = (N + GT - 1) / GT;
+    hipLaunchKernelGGL(zgemm_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, s, M, N, K, A, lda, transA, B,
+                       ldb, transB, C, ldc, alpha, beta, 2, tri_k, 0, 0LL);
+    return hipGetLastError();
+  }
   dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
   hipLaunchKernelGGL(zgemm_kernel, grid, dim3(256), 0, s, M, N, K, A, lda, transA, B, ldb, transB, C, ldc, alpha,
                      beta, lower_only, tri_k, 0, 0LL);
