@@ -30,7 +30,9 @@ hipError_t launch_scale_table(const double *e_v, int nv, const double *e_c, int 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int PP_THREADS = 256;
-constexpr int PP_CHUNK = 2 * PP_THREADS;   // grid points per workgroup
+constexpr int PP_NH = 2;                                 // point pairs per thread, 128 points apart
+constexpr int PP_SEG = 2 * 64 * PP_NH;                   // consecutive points per wave
+constexpr int PP_CHUNK = (PP_THREADS / 64) * PP_SEG;     // grid points per workgroup
 
 __device__ __forceinline__ float2 conj_mul_scale(float2 v, float2 c, float s) {
   // conj(v) * c * s
@@ -40,47 +42,66 @@ __device__ __forceinline__ float2 conj_mul_scale(float2 v, float2 c, float s) {
 constexpr int PP_VB = 8;   // occupied bands whose psi_v values a thread holds in registers
 constexpr int PP_CG = 8;   // unoccupied bands per workgroup (4: 4.4 TB/s, 8: 4.7, 16: 4.5 at 36^3)
 
+// Lane l of wave w holds the point pairs (p, p + 1), p = chunk + w PP_SEG + 2 l + 128 h, h < PP_NH: for
+// each (v, c) a wave's PP_NH stores cover PP_NH KB of one row of F back to back.
 __global__ __launch_bounds__(PP_THREADS) void pair_products_kernel(const float2 *__restrict__ psi_v, int nv,
                                                                    const float2 *__restrict__ psi_c, int nc, int nr,
                                                                    const float *__restrict__ scale, int ldsc,
                                                                    float2 *__restrict__ f) {
-  const int r0 = blockIdx.x * PP_CHUNK + 2 * threadIdx.x;   // chunk fastest: neighbours write one row's stream
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int base = blockIdx.x * PP_CHUNK + wave * PP_SEG + 2 * lane;
   const int cg0 = blockIdx.y * PP_CG;
-  if (r0 >= nr) return;
-  const bool two = (r0 + 1 < nr);
-  const bool wide = two && ((nr & 1) == 0);
+  if (base >= nr) return;   // the thread's first point is its smallest
+  bool one[PP_NH], two[PP_NH], wide[PP_NH];
+#pragma unroll
+  for (int h = 0; h < PP_NH; ++h) {
+    const int p = base + 128 * h;
+    one[h] = p < nr;
+    two[h] = p + 1 < nr;
+    wide[h] = two[h] && ((nr & 1) == 0);
+  }
   for (int vb = 0; vb < nv; vb += PP_VB) {
     const int nvb = min(PP_VB, nv - vb);
-    float2 v0[PP_VB], v1[PP_VB];
+    float2 v0[PP_NH][PP_VB], v1[PP_NH][PP_VB];
 #pragma unroll
-    for (int k = 0; k < PP_VB; ++k) {
-      v0[k] = make_float2(0.f, 0.f);
-      v1[k] = make_float2(0.f, 0.f);
-      if (k < nvb) {
-        const float2 *pv = psi_v + (size_t)(vb + k) * nr + r0;
-        v0[k] = pv[0];
-        if (two) v1[k] = pv[1];
+    for (int h = 0; h < PP_NH; ++h)
+#pragma unroll
+      for (int k = 0; k < PP_VB; ++k) {
+        v0[h][k] = make_float2(0.f, 0.f);
+        v1[h][k] = make_float2(0.f, 0.f);
+        if (k < nvb && one[h]) {
+          const float2 *pv = psi_v + (size_t)(vb + k) * nr + base + 128 * h;
+          v0[h][k] = pv[0];
+          if (two[h]) v1[h][k] = pv[1];
+        }
       }
-    }
     for (int cc = 0; cc < PP_CG; ++cc) {
       const int c = cg0 + cc;
       if (c >= nc) break;
-      const float2 *pc = psi_c + (size_t)c * nr + r0;
-      const float2 c0 = pc[0];
-      const float2 c1 = two ? pc[1] : make_float2(0.f, 0.f);
+      float2 c0[PP_NH], c1[PP_NH];
+#pragma unroll
+      for (int h = 0; h < PP_NH; ++h) {
+        const float2 *pc = psi_c + (size_t)c * nr + base + 128 * h;
+        c0[h] = one[h] ? pc[0] : make_float2(0.f, 0.f);
+        c1[h] = two[h] ? pc[1] : make_float2(0.f, 0.f);
+      }
 #pragma unroll
       for (int k = 0; k < PP_VB; ++k) {
         if (k < nvb) {
           const float s = scale[(vb + k) * ldsc + c];
-          float2 *out = f + ((size_t)(vb + k) * nc + c) * nr + r0;
-          const float2 a = conj_mul_scale(v0[k], c0, s);
-          if (wide) {
-            const float2 b = conj_mul_scale(v1[k], c1, s);
-            const f32x4 w = {a.x, a.y, b.x, b.y};
-            __builtin_nontemporal_store(w, reinterpret_cast<f32x4 *>(out));
-          } else {
-            out[0] = a;
-            if (two) out[1] = conj_mul_scale(v1[k], c1, s);
+#pragma unroll
+          for (int h = 0; h < PP_NH; ++h) {
+            if (!one[h]) continue;
+            float2 *out = f + ((size_t)(vb + k) * nc + c) * nr + base + 128 * h;
+            const float2 a = conj_mul_scale(v0[h][k], c0[h], s);
+            if (wide[h]) {
+              const float2 b = conj_mul_scale(v1[h][k], c1[h], s);
+              const f32x4 w = {a.x, a.y, b.x, b.y};
+              __builtin_nontemporal_store(w, reinterpret_cast<f32x4 *>(out));
+            } else {
+              out[0] = a;
+              if (two[h]) out[1] = conj_mul_scale(v1[h][k], c1[h], s);
+            }
           }
         }
       }
