@@ -253,13 +253,16 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
     if (i < nb && j < nb && j <= i) v = A[(size_t)(k0 + i) * n + k0 + j];
     if (i >= nb && i == j) v = make_double2(1.0, 0.0);      // pad with identity
     a[i][j] = v;
+    x[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
-  __syncthreads();
-  // unblocked right-looking Cholesky on the lower triangle, with unscaled columns: step j subtracts
-  // s_j s_j^H / d_j (d_j the pivot) from the trailing lower triangle, which needs one barrier per
-  // step; column j is final after step j and is scaled to L in one pass at the end.  A thread owns
-  // column m = tid % NB of rows tid / NB + 8t; step j writes only columns m > j, so every read of the
-  // step (column j and the thread's four entries) is issued before its first write.
+  // Unblocked right-looking Cholesky on the lower triangle, with unscaled columns: step j subtracts
+  // s_j s_j^H / d_j (d_j the pivot, s_j column j) from the trailing lower triangle, one barrier per step.
+  // In elimination form A = Lu D Lu^H with Lu = I + sum_j (s_j / d_j) e_j^T below the diagonal, so the
+  // same step also applies Lu's j-th elimination to X (started as I): row i > j loses (s_j(i) / d_j)
+  // times row j, on the columns m <= j where row j is non-zero.  After the last step X = Lu^-1, and
+  // L = Lu D^1/2, L^-1 = D^-1/2 X follow by scaling.  A thread owns column m = tid % NB of rows
+  // tid / NB + 8t: for each row the factor update (m > j) and the X update (m <= j) are disjoint, and
+  // neither writes column j of a or row j of X, so every read of the step is issued before its writes.
   {
     const int m = tid % NB, ib = tid / NB;
     for (int j = 0; j < NB; ++j) {
@@ -270,12 +273,13 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
         d = 1.0;
       }
       const double dinv = 1.0 / d;
-      const double2 q = a[m][j];
-      double2 p[NB * NB / 256], c[NB * NB / 256];
+      const double2 q = a[m][j], xq = x[j][m];
+      double2 p[NB * NB / 256], c[NB * NB / 256], xc[NB * NB / 256];
 #pragma unroll
       for (int t = 0; t < NB * NB / 256; ++t) {
         p[t] = a[ib + 8 * t][j];
         c[t] = a[ib + 8 * t][m];
+        xc[t] = x[ib + 8 * t][m];
       }
 #pragma unroll
       for (int t = 0; t < NB * NB / 256; ++t) {
@@ -284,57 +288,33 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
           c[t].x -= (p[t].x * q.x + p[t].y * q.y) * dinv;
           c[t].y -= (p[t].y * q.x - p[t].x * q.y) * dinv;
           a[i][m] = c[t];
+        } else if (m <= j && i > j) {
+          const double lr = p[t].x * dinv, li = p[t].y * dinv;
+          xc[t].x -= lr * xq.x - li * xq.y;
+          xc[t].y -= lr * xq.y + li * xq.x;
+          x[i][m] = xc[t];
         }
       }
     }
   }
   __syncthreads();
-  // L = column j over sqrt(d_j) (bad pivots were replaced by 1 and flagged)
+  // r_j = sqrt(d_j) (bad pivots were replaced by 1 and flagged); L = column j over r_j, L^-1 = row i of X
+  // over r_i
+  __shared__ double rs[NB];
+  if (tid < NB) {
+    double d = a[tid][tid].x;
+    if (!(d > 0.0) || !isfinite(d)) d = 1.0;
+    rs[tid] = sqrt(d);
+  }
+  __syncthreads();
   for (int idx = tid; idx < NB * NB; idx += 256) {
     const int i = idx / NB, j = idx % NB;
     if (j <= i) {
-      double d = a[j][j].x;
-      if (!(d > 0.0) || !isfinite(d)) d = 1.0;
-      const double r = sqrt(d);
-      x[i][j] = (i == j) ? make_double2(r, 0.0) : make_double2(a[i][j].x / r, a[i][j].y / r);
+      const double r = rs[j];
+      a[i][j] = (i == j) ? make_double2(r, 0.0) : make_double2(a[i][j].x / r, a[i][j].y / r);
     }
-  }
-  __syncthreads();
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int i = idx / NB, j = idx % NB;
-    if (j <= i) a[i][j] = x[i][j];
-  }
-  __syncthreads();
-  // inverse of the lower-triangular factor by forward substitution on each unit vector, L x = e_col:
-  // eight lanes per column split the dot product over m and reduce it with shuffles; a column's eight
-  // lanes sit in one wave, so the rows of one column need no workgroup barrier between them.  Lane
-  // `part` takes m = part + 8s for all four s with m < i: a fixed trip count whose loads issue together
-  // (x[m][col] is already zero for m < col, so starting below col adds only zeros).
-  {
-    const int col = tid >> 3, part = tid & 7;
-    for (int i = 0; i < NB; ++i) {
-      double sr = 0.0, si = 0.0;
-#pragma unroll
-      for (int s4 = 0; s4 < NB / 8; ++s4) {
-        const int m = part + 8 * s4;
-        const double2 l = a[i][m], v = x[m][col];
-        if (m < i) {
-          sr += l.x * v.x - l.y * v.y;
-          si += l.x * v.y + l.y * v.x;
-        }
-      }
-      for (int off = 4; off > 0; off >>= 1) {
-        sr += __shfl_xor(sr, off, 8);
-        si += __shfl_xor(si, off, 8);
-      }
-      if (part == 0) {
-        const double d = a[i][i].x;
-        const double er = (i == col ? 1.0 : 0.0) - sr;
-        x[i][col] = (i < col) ? make_double2(0.0, 0.0) : make_double2(er / d, -si / d);
-      }
-      __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this wave's LDS write lands before the next row reads it
-      __builtin_amdgcn_wave_barrier();
-    }
+    const double ri = rs[i];
+    x[i][j] = make_double2(x[i][j].x / ri, x[i][j].y / ri);
   }
   __syncthreads();
   if (blockIdx.x == 0) {
