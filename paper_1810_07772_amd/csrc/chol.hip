@@ -407,10 +407,33 @@ __global__ __launch_bounds__(256) void subst_panel_kernel(const double2 *__restr
     const int i = idx / SUB_CW, c = idx % SUB_CW;
     sB[i][c] = (i < rows && c0 + c < n) ? B[(size_t)(p0 + i) * n + c0 + c] : make_double2(0.0, 0.0);
   }
+  // The 32 x 32 blocks pass through sM in the order Linv_(k0), L_(k0+32, k0), ..., Linv_(k0+32), ...; each
+  // is loaded into registers (pf) while the block before it is in use, and written to sM when that is free.
+  double2 pf[NB * NB / 256];
+  auto fetch = [&](int k0, int j0) {   // j0 < 0: Linv of block k0; else L[j0 : j0 + 32, k0 : k0 + 32], zero-padded
+    const int nb = min(NB, n - k0), jn = min(NB, p1 - j0);
+#pragma unroll
+    for (int t = 0; t < NB * NB / 256; ++t) {
+      const int idx = tid + 256 * t, i = idx / NB, m = idx % NB;
+      if (j0 < 0)
+        pf[t] = linv_all[(size_t)(k0 / NB) * NB * NB + idx];
+      else
+        pf[t] = (i < jn && m < nb) ? L[(size_t)(j0 + i) * n + k0 + m] : make_double2(0.0, 0.0);
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int t = 0; t < NB * NB / 256; ++t) {
+      const int idx = tid + 256 * t;
+      sM[idx / NB][idx % NB] = pf[t];
+    }
+  };
+  fetch(p0, -1);
   for (int k0 = p0; k0 < p1; k0 += NB) {
     const int nb = min(NB, n - k0), kr = k0 - p0;
-    for (int idx = tid; idx < NB * NB; idx += 256) sM[idx / NB][idx % NB] = linv_all[(size_t)(k0 / NB) * NB * NB + idx];
+    commit();
     __syncthreads();
+    if (k0 + NB < p1) fetch(k0, k0 + NB);
     // X_k = Linv_kk B_k.  Linv_kk is stored with zeros above its diagonal, so m runs over the whole
     // block for every thread: thread (i = ib + 8t, c) keeps PER independent sums.
     const int ib = tid / SUB_CW, c = tid % SUB_CW;
@@ -440,11 +463,12 @@ __global__ __launch_bounds__(256) void subst_panel_kernel(const double2 *__restr
     for (int j0 = k0 + NB; j0 < p1; j0 += NB) {
       const int jn = min(NB, p1 - j0), jr = j0 - p0;
       __syncthreads();
-      for (int idx = tid; idx < NB * NB; idx += 256) {
-        const int i = idx / NB, m = idx % NB;
-        sM[i][m] = (i < jn && m < nb) ? L[(size_t)(j0 + i) * n + k0 + m] : make_double2(0.0, 0.0);
-      }
+      commit();
       __syncthreads();
+      if (j0 + NB < p1)
+        fetch(k0, j0 + NB);
+      else if (k0 + NB < p1)
+        fetch(k0 + NB, -1);
       // sM is zero for m >= nb, so m runs over the whole block here too
       double2 acc[PER];
 #pragma unroll
