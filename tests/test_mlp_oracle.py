@@ -100,3 +100,62 @@ def test_mlp_init_layout():
     assert v.dtype == np.float32 and v.size == 21409
     p = mo.unflatten(v)
     assert p["b3"][0] == -2.0 and np.all(p["b1"] == 0)
+
+
+# ---------------------------------------------------------------------------------------------
+# Hand values of the feature map, the activations and the output head.  The features are the
+# reading of the learned tail's per-G inputs (band truncation of Eq.(Pstatic), the paper's first
+# technical issue): |q+G| in 1/Bohr with G = (2 pi / a) m, log |Re P~_Nc(G,G)|, Nc / N_g and E_max.
+# Every expected number below is written out from its closed form (30-digit evaluation), not from
+# the oracle.
+# ---------------------------------------------------------------------------------------------
+def test_features_hand_values():
+    a_bohr = 4.0                                  # 2 pi / a = pi / 2
+    q = [0.0, 0.0, 0.5]
+    miller = [[0, 0, 0], [2, 1, -1], [-1, 2, 2]]  # |q+m|^2 = 0.25, 5.25, 11.25
+    pt = np.array([[-2.0 + 3.0j, 7.0 - 1.0j, 5.0 + 5.0j],
+                   [7.0 + 1.0j, -0.5 - 0.25j, -9.0 + 2.0j],
+                   [5.0 - 5.0j, -9.0 - 2.0j, 1e-40 + 4.0j]])
+    x = mo.features(pt, q, miller, a_bohr, nc=6, e_max=0.3125)
+    assert x.shape == (3, 4)
+    # |q+G| = (pi/2) sqrt(0.25), (pi/2) sqrt(5.25), (pi/2) sqrt(11.25)
+    np.testing.assert_allclose(x[:, 0], [0.785398163397448309615660845820, 3.59914653444810207094217103239,
+                                         5.26861104828054479486728098240], rtol=1e-15)
+    # log |Re P~(G,G)|: log 2, log 0.5, and the 1e-30 floor for a vanishing real part
+    np.testing.assert_allclose(x[:, 1], [0.693147180559945309417232121458, -0.693147180559945309417232121458,
+                                         -69.0775527898213705205397436405], rtol=1e-15)
+    # Nc / N_g = 6 / 3 and E_max on every row
+    assert np.array_equal(x[:, 2], [2.0, 2.0, 2.0])
+    assert np.array_equal(x[:, 3], [0.3125, 0.3125, 0.3125])
+
+
+def test_activation_hand_values():
+    z = np.array([0.0, 1.0, -2.0, 3.0])
+    # silu(z) = z / (1 + e^-z): 0, e/(1+e), -2/(1+e^2), 3/(1+e^-3)
+    np.testing.assert_allclose(mo.silu(z), [0.0, 0.731058578630004879251159241822,
+                                            -0.238405844044235111880541717395, 2.85772238046729965736345554468],
+                               rtol=1e-15, atol=0)
+    # silu'(z) = sigma(z) (1 + z (1 - sigma(z))): 1/2 at 0
+    np.testing.assert_allclose(mo.dsilu(np.array([0.0, 1.0, -2.0])),
+                               [0.5, 0.927670511871486731788583975408, -0.0907842487848954787569775108232],
+                               rtol=1e-14)
+    # softplus(z) = log(1 + e^z): log 2, log(1+e), log(1+e^-3), e^-30 to first order, 40 (+4e-18)
+    np.testing.assert_allclose(mo.softplus(np.array([0.0, 1.0, -3.0, -30.0, 40.0])),
+                               [0.693147180559945309417232121458, 1.31326168751822283404899549497,
+                                0.0485873515737420587589259198547, 9.35762296883973677414241121536e-14, 40.0],
+                               rtol=1e-14)
+
+
+def test_head_hand_values():
+    """d = softplus(o_0) s and u_k = (o_{1+k} + i o_{17+k}) sqrt(s) on one G row."""
+    o = np.zeros((1, 33))
+    o[0, 0] = 0.0
+    o[0, 1], o[0, 17] = 3.0, -4.0      # u_0 = (3 - 4i) sqrt(s)
+    o[0, 16], o[0, 32] = 0.5, 0.25     # u_15 = (0.5 + 0.25i) sqrt(s)
+    s = np.array([4.0])
+    d, u = mo.head(o, s)
+    np.testing.assert_allclose(d, [4.0 * 0.693147180559945309417232121458], rtol=1e-15)
+    assert u.shape == (1, 16)
+    assert u[0, 0] == 6.0 - 8.0j and u[0, 15] == 1.0 + 0.5j and np.all(u[0, 1:15] == 0)
+    # the correction is -(d + |u|^2) on the diagonal: -(4 log 2 + 100 + 1.25)
+    np.testing.assert_allclose(mo.correction(o, s), [[-(2.77258872223978123766892848583 + 101.25)]], rtol=1e-15)
