@@ -172,6 +172,56 @@ def _dev(t, dtype=None, name="tensor"):
     return C.c_void_p(t.data_ptr())
 
 
+def _shape(t, shape, name):
+    """Raise ValueError unless tensor t (on any device) has exactly this shape.  Runs before any
+    library or device call, so a mismatched buffer never reaches a kernel."""
+    got = tuple(int(x) for x in getattr(t, "shape", ()))
+    want = tuple(int(x) for x in shape)
+    if got != want:
+        raise ValueError(f"{name} has shape {got}, expected {want}")
+
+
+def _ndim(t, nd, name):
+    got = tuple(int(x) for x in getattr(t, "shape", ()))
+    if len(got) != nd:
+        raise ValueError(f"{name} must have {nd} dimensions, got shape {got}")
+    return got
+
+
+def _len(a, n, name):
+    m = int(np.size(a))
+    if m != int(n):
+        raise ValueError(f"{name} has {m} entries, expected {int(n)}")
+
+
+def _nr_of(n) -> int:
+    nt = tuple(int(x) for x in (n if np.ndim(n) else (n, n, n)))
+    if len(nt) != 3:
+        raise ValueError(f"grid must have three lengths, got {nt}")
+    return nt[0] * nt[1] * nt[2]
+
+
+def _miller_rows(miller, name="g_miller"):
+    m = np.asarray(miller)
+    if m.ndim != 2 or m.shape[1] != 3:
+        raise ValueError(f"{name} must be [ng][3], got shape {m.shape}")
+    return m.shape[0]
+
+
+def _orbitals(psi_v, psi_c, e_v, e_c, nr=None):
+    """(nv, nc, nr) of an occupied/unoccupied pair of orbital arrays, checked against each other,
+    against the energies and (if given) against the grid size."""
+    nv, nrv = _ndim(psi_v, 2, "psi_v")
+    nc, nrc = _ndim(psi_c, 2, "psi_c")
+    if nrv != nrc:
+        raise ValueError(f"psi_v has {nrv} grid points per band, psi_c {nrc}")
+    if nr is not None and nrv != nr:
+        raise ValueError(f"orbitals have {nrv} grid points, the grid has {nr}")
+    _len(e_v, nv, "e_v")
+    _len(e_c, nc, "e_c")
+    return nv, nc, nrv
+
+
 def _host_f64(a, name):
     a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
     return a, a.ctypes.data_as(C.c_void_p)
@@ -212,7 +262,9 @@ def mfma_rate(words, n_iter, grid, out=None, ctx: Optional[Context] = None):
     import torch
     if words.numel() != 4096:
         raise ValueError("words must hold 4096 uint32 words")
-    if out is None:
+    if out is not None:
+        _shape(out, (int(grid) * 512,), "out")
+    else:
         out = torch.empty(int(grid) * 512, dtype=torch.float32, device=words.device)
     ctx = ctx or context(words.device.index)
     st = ctx.lib.gw_mfma_rate(ctx.handle, _dev(words, torch.int32, "words"), int(n_iter), int(grid),
@@ -232,9 +284,10 @@ def default_tile_name(precision="fp32", nr=0):
 # ---------------------------------------------------------------------------------------------
 def pair_products(psi_v, psi_c, e_v, e_c, prefactor=1.0, out=None, ctx: Optional[Context] = None):
     import torch
-    nv, nr = psi_v.shape
-    nc = psi_c.shape[0]
-    if out is None:
+    nv, nc, nr = _orbitals(psi_v, psi_c, e_v, e_c)
+    if out is not None:
+        _shape(out, (nv * nc, nr), "f_out")
+    else:
         out = torch.empty((nv * nc, nr), dtype=torch.complex64, device=psi_v.device)
     ctx = ctx or context(psi_v.device.index)
     ev, pev = _host_f64(e_v, "e_v")
@@ -249,9 +302,10 @@ def pair_products(psi_v, psi_c, e_v, e_c, prefactor=1.0, out=None, ctx: Optional
 def polarizability_r(psi_v, psi_c, e_v, e_c, precision="fp32", prefactor=1.0, accumulate=False, tile=-1, out=None,
                      ctx: Optional[Context] = None):
     import torch
-    nv, nr = psi_v.shape
-    nc = psi_c.shape[0]
-    if out is None:
+    nv, nc, nr = _orbitals(psi_v, psi_c, e_v, e_c)
+    if out is not None:
+        _shape(out, (nr, nr), "p_rr")
+    else:
         out = torch.empty((nr, nr), dtype=torch.complex64, device=psi_v.device)
     ctx = ctx or context(psi_v.device.index)
     ev, pev = _host_f64(e_v, "e_v")
@@ -266,9 +320,13 @@ def polarizability_r(psi_v, psi_c, e_v, e_c, precision="fp32", prefactor=1.0, ac
 
 def sphere_transform(p_rr, n, miller, out=None, ctx: Optional[Context] = None):
     import torch
+    nr = _nr_of(n)
+    ng = _miller_rows(miller)
+    _shape(p_rr, (nr, nr), "p_rr")
     m, pm = _host_i32(miller, "g_miller")
-    ng = m.shape[0]
-    if out is None:
+    if out is not None:
+        _shape(out, (ng, ng), "p_gg")
+    else:
         out = torch.empty((ng, ng), dtype=torch.complex64, device=p_rr.device)
     ctx = ctx or context(p_rr.device.index)
     st = ctx.lib.gw_sphere_transform(ctx.handle, _dev(p_rr, torch.complex64, "p_rr"), _grid(n, 1.0), pm, ng,
@@ -280,12 +338,17 @@ def sphere_transform(p_rr, n, miller, out=None, ctx: Optional[Context] = None):
 def polarizability(psi_v, psi_c, e_v, e_c, n, a_bohr, q, miller, precision="fp32", prefactor=1.0, accumulate=False,
                    tile=-1, p_rr=None, out=None, ctx: Optional[Context] = None):
     import torch
-    nv = psi_v.shape[0]
-    nc = psi_c.shape[0]
+    nr = _nr_of(n)
+    nv, nc, _ = _orbitals(psi_v, psi_c, e_v, e_c, nr)
+    ng = _miller_rows(miller)
+    _len(q, 3, "q")
+    if p_rr is not None:
+        _shape(p_rr, (nr, nr), "p_rr")
     m, pm = _host_i32(miller, "g_miller")
-    ng = m.shape[0]
     qa, pq = _host_f64(q, "q")
-    if out is None:
+    if out is not None:
+        _shape(out, (ng, ng), "p_gg")
+    else:
         out = torch.empty((ng, ng), dtype=torch.complex64, device=psi_v.device)
     ctx = ctx or context(psi_v.device.index)
     ev, pev = _host_f64(e_v, "e_v")
@@ -301,10 +364,14 @@ def polarizability(psi_v, psi_c, e_v, e_c, n, a_bohr, q, miller, precision="fp32
 
 def epsilon(p_gg, n, a_bohr, q, miller, head=1.0, out=None, ctx: Optional[Context] = None):
     import torch
+    ng = _miller_rows(miller)
+    _len(q, 3, "q")
+    _shape(p_gg, (ng, ng), "p_gg")
     m, pm = _host_i32(miller, "g_miller")
-    ng = m.shape[0]
     qa, pq = _host_f64(q, "q")
-    if out is None:
+    if out is not None:
+        _shape(out, (ng, ng), "eps_out")
+    else:
         out = torch.empty((ng, ng), dtype=torch.complex128, device=p_gg.device)
     ctx = ctx or context(p_gg.device.index)
     st = ctx.lib.gw_epsilon(ctx.handle, _dev(p_gg, torch.complex64, "p_gg"), ng, _grid(n, a_bohr), pq, pm,
@@ -315,10 +382,14 @@ def epsilon(p_gg, n, a_bohr, q, miller, head=1.0, out=None, ctx: Optional[Contex
 
 def eps_inverse(p_gg, n, a_bohr, q, miller, head=1.0, out=None, ctx: Optional[Context] = None):
     import torch
+    ng = _miller_rows(miller)
+    _len(q, 3, "q")
+    _shape(p_gg, (ng, ng), "p_gg")
     m, pm = _host_i32(miller, "g_miller")
-    ng = m.shape[0]
     qa, pq = _host_f64(q, "q")
-    if out is None:
+    if out is not None:
+        _shape(out, (ng, ng), "eps_inv")
+    else:
         out = torch.empty((ng, ng), dtype=torch.complex128, device=p_gg.device)
     ctx = ctx or context(p_gg.device.index)
     st = ctx.lib.gw_eps_inverse(ctx.handle, _dev(p_gg, torch.complex64, "p_gg"), ng, _grid(n, a_bohr), pq, pm,
@@ -329,8 +400,11 @@ def eps_inverse(p_gg, n, a_bohr, q, miller, head=1.0, out=None, ctx: Optional[Co
 
 def hpd_inverse(a, out=None, ctx: Optional[Context] = None):
     import torch
-    n = a.shape[0]
-    if out is None:
+    n = _ndim(a, 2, "a")[0]
+    _shape(a, (n, n), "a")
+    if out is not None:
+        _shape(out, (n, n), "out")
+    else:
         out = torch.empty_like(a)
     ctx = ctx or context(a.device.index)
     st = ctx.lib.gw_hpd_inverse(ctx.handle, _dev(a, torch.complex128, "a"), n, _dev(out, torch.complex128, "out"),
@@ -342,8 +416,9 @@ def hpd_inverse(a, out=None, ctx: Optional[Context] = None):
 def autotune(psi_v, psi_c, e_v, e_c, precision="bf16", p_scratch=None, ctx: Optional[Context] = None):
     """Times every update tile of `precision` on these inputs; returns (best tile, {name: ms})."""
     import torch
-    nv, nr = psi_v.shape
-    nc = psi_c.shape[0]
+    nv, nc, nr = _orbitals(psi_v, psi_c, e_v, e_c)
+    if p_scratch is not None:
+        _shape(p_scratch, (nr, nr), "p_scratch")
     ctx = ctx or context(psi_v.device.index)
     if p_scratch is None:
         p_scratch = torch.empty((nr, nr), dtype=torch.complex64, device=psi_v.device)
@@ -364,12 +439,14 @@ def autotune(psi_v, psi_c, e_v, e_c, precision="bf16", p_scratch=None, ctx: Opti
 def orbitals_to_grid(coeff, n, pw_miller, out=None, ctx: Optional[Context] = None):
     """psi [nb][N_r] complex64 on the grid from plane-wave coefficients [nb][npw] on the device."""
     import torch
+    nb, npw = _ndim(coeff, 2, "coeff")
+    if _miller_rows(pw_miller, "pw_miller") != npw:
+        raise ValueError(f"pw_miller has {np.asarray(pw_miller).shape[0]} rows for {npw} coefficients")
     m, pm = _host_i32(pw_miller, "pw_miller")
-    nb, npw = coeff.shape
-    if m.shape[0] != npw:
-        raise ValueError(f"pw_miller has {m.shape[0]} rows for {npw} coefficients")
     nt = tuple(int(x) for x in (n if np.ndim(n) else (n, n, n)))
-    nr = nt[0] * nt[1] * nt[2]
+    nr = _nr_of(nt)
+    if out is not None:
+        _shape(out, (nb, nr), "psi")
     if out is None:
         out = torch.empty((nb, nr), dtype=torch.complex64, device=coeff.device)
     ctx = ctx or context(coeff.device.index)
@@ -385,8 +462,13 @@ def plasmon_pole(eps_inv, n, a_bohr, q, miller, psi_v, occupation=1.0, n_modes=8
     frequencies.  Returns (sigma [n_modes] f64, omega [n_modes] f64, modes [ng][n_modes] c128 on the
     device, iterations, final relative residual)."""
     import torch
+    ng = _miller_rows(miller)
+    _len(q, 3, "q")
+    _shape(eps_inv, (ng, ng), "eps_inv")
+    _ndim(psi_v, 2, "psi_v")
+    if psi_v.shape[1] != _nr_of(n):
+        raise ValueError(f"psi_v has {psi_v.shape[1]} grid points, the grid has {_nr_of(n)}")
     m, pm = _host_i32(miller, "g_miller")
-    ng = m.shape[0]
     qa, pq = _host_f64(q, "q")
     dev = eps_inv.device
     sigma = torch.empty(n_modes, dtype=torch.float64, device=dev)
@@ -407,11 +489,18 @@ def pp_eps_inverse(eps_inv_static, n, a_bohr, q, miller, modes, sigma, omega, fr
                    ctx: Optional[Context] = None):
     """eps^-1(w) of the pole form for each frequency in freqs (Hartree): [nf][ng][ng] complex128."""
     import torch
+    ng = _miller_rows(miller)
+    _len(q, 3, "q")
+    _shape(eps_inv_static, (ng, ng), "eps_inv_static")
+    nm = _ndim(modes, 2, "modes")[1]
+    _shape(modes, (ng, nm), "modes")
+    _shape(sigma, (nm,), "sigma")
+    _shape(omega, (nm,), "omega")
     m, pm = _host_i32(miller, "g_miller")
-    ng = m.shape[0]
     qa, pq = _host_f64(q, "q")
     fr, pf = _host_f64(np.atleast_1d(np.asarray(freqs, np.float64)), "freqs")
-    nm = modes.shape[1]
+    if out is not None:
+        _shape(out, (len(fr), ng, ng), "out")
     if out is None:
         out = torch.empty((len(fr), ng, ng), dtype=torch.complex128, device=modes.device)
     ctx = ctx or context(modes.device.index)
@@ -428,10 +517,17 @@ def sigma_static(psi_n, psi_v, n, a_bohr, q, miller, eps_inv=None, want_x=True,
     """(sigma_x, sigma_sex) [nn][nn] complex128 on the device; sigma_sex is None without eps_inv and
     sigma_x is None when want_x is False."""
     import torch
+    ng = _miller_rows(miller)
+    _len(q, 3, "q")
+    nr = _nr_of(n)
+    nn, nrn = _ndim(psi_n, 2, "psi_n")
+    nv, nrv = _ndim(psi_v, 2, "psi_v")
+    if nrn != nr or nrv != nr:
+        raise ValueError(f"psi_n / psi_v have {nrn} / {nrv} grid points, the grid has {nr}")
+    if eps_inv is not None:
+        _shape(eps_inv, (ng, ng), "eps_inv")
     m, pm = _host_i32(miller, "g_miller")
-    ng = m.shape[0]
     qa, pq = _host_f64(q, "q")
-    nn, nv = psi_n.shape[0], psi_v.shape[0]
     dev = psi_n.device
     sx = torch.empty((nn, nn), dtype=torch.complex128, device=dev) if want_x else None
     ss = torch.empty((nn, nn), dtype=torch.complex128, device=dev) if eps_inv is not None else None
@@ -448,9 +544,16 @@ def sigma_static(psi_n, psi_v, n, a_bohr, q, miller, eps_inv=None, want_x=True,
 def sigma_sex_modes(psi_n, psi_v, n, miller, modes, sigma, ctx: Optional[Context] = None):
     """Screened exchange [nn][nn] complex128 from the plasmon-pole modes (eigen form)."""
     import torch
+    ng = _miller_rows(miller)
+    nr = _nr_of(n)
+    nn, nrn = _ndim(psi_n, 2, "psi_n")
+    nv, nrv = _ndim(psi_v, 2, "psi_v")
+    if nrn != nr or nrv != nr:
+        raise ValueError(f"psi_n / psi_v have {nrn} / {nrv} grid points, the grid has {nr}")
+    nm = _ndim(modes, 2, "modes")[1]
+    _shape(modes, (ng, nm), "modes")
+    _shape(sigma, (nm,), "sigma")
     m, pm = _host_i32(miller, "g_miller")
-    ng = m.shape[0]
-    nn, nv = psi_n.shape[0], psi_v.shape[0]
     out = torch.empty((nn, nn), dtype=torch.complex128, device=psi_n.device)
     ctx = ctx or context(psi_n.device.index)
     st = ctx.lib.gw_sigma_sex_modes(ctx.handle, _dev(psi_n, torch.complex64, "psi_n"), nn,
@@ -464,8 +567,11 @@ def sigma_sex_modes(psi_n, psi_v, n, miller, modes, sigma, ctx: Optional[Context
 def newton_inverse(a, tol=1e-11, max_iter=100, out=None, ctx: Optional[Context] = None):
     """Inverse by the Newton iteration; returns (inverse, iterations, max-change history)."""
     import torch
-    n = a.shape[0]
-    if out is None:
+    n = _ndim(a, 2, "a")[0]
+    _shape(a, (n, n), "a")
+    if out is not None:
+        _shape(out, (n, n), "out")
+    else:
         out = torch.empty_like(a)
     ctx = ctx or context(a.device.index)
     its = C.c_int(0)
@@ -479,10 +585,14 @@ def newton_inverse(a, tol=1e-11, max_iter=100, out=None, ctx: Optional[Context] 
 def eps_inverse_newton(p_gg, n, a_bohr, q, miller, head=1.0, tol=1e-11, max_iter=100, out=None,
                        ctx: Optional[Context] = None):
     import torch
+    ng = _miller_rows(miller)
+    _len(q, 3, "q")
+    _shape(p_gg, (ng, ng), "p_gg")
     m, pm = _host_i32(miller, "g_miller")
-    ng = m.shape[0]
     qa, pq = _host_f64(q, "q")
-    if out is None:
+    if out is not None:
+        _shape(out, (ng, ng), "eps_inv")
+    else:
         out = torch.empty((ng, ng), dtype=torch.complex128, device=p_gg.device)
     ctx = ctx or context(p_gg.device.index)
     its = C.c_int(0)
@@ -498,7 +608,21 @@ def polarizability_batched(psi_v, e_v, n, a_bohr, jobs, precision="fp32", prefac
                            ctx: Optional[Context] = None):
     """jobs: list of dicts with psi_c (device), e_c, q, miller (host), p_gg and optional eps_inv (device)."""
     import torch
-    nv = psi_v.shape[0]
+    nr = _nr_of(n)
+    nv, nrv = _ndim(psi_v, 2, "psi_occ")
+    if nrv != nr:
+        raise ValueError(f"psi_occ has {nrv} grid points, the grid has {nr}")
+    _len(e_v, nv, "e_v")
+    for j, job in enumerate(jobs):
+        nc, nrc = _ndim(job["psi_c"], 2, f"jobs[{j}].psi_c")
+        if nrc != nr:
+            raise ValueError(f"jobs[{j}].psi_c has {nrc} grid points, the grid has {nr}")
+        _len(job["e_c"], nc, f"jobs[{j}].e_c")
+        _len(job["q"], 3, f"jobs[{j}].q")
+        ng = _miller_rows(job["miller"], f"jobs[{j}].miller")
+        _shape(job["p_gg"], (ng, ng), f"jobs[{j}].p_gg")
+        if job.get("eps_inv") is not None:
+            _shape(job["eps_inv"], (ng, ng), f"jobs[{j}].eps_inv")
     ctx = ctx or context(psi_v.device.index)
     ev, pev = _host_f64(e_v, "e_v")
     keep = []
@@ -558,8 +682,11 @@ class TailModel:
 
     def forward(self, feat, out=None):
         import torch
-        ng = feat.shape[0]
-        if out is None:
+        ng = _ndim(feat, 2, "feat")[0]
+        _shape(feat, (ng, 4), "feat")
+        if out is not None:
+            _shape(out, (ng, 33), "out")
+        else:
             out = torch.empty((ng, 33), dtype=torch.float32, device=feat.device)
         st = self.ctx.lib.gw_tail_forward(self.ctx.handle, C.byref(self.mlp), _dev(feat, torch.float32, "feat"), ng,
                                           _dev(out, torch.float32, "out"), _stream(feat))
@@ -568,8 +695,12 @@ class TailModel:
 
     def train_step(self, feat, target, loss_out=None):
         import torch
-        ng = feat.shape[0]
-        if loss_out is None:
+        ng = _ndim(feat, 2, "feat")[0]
+        _shape(feat, (ng, 4), "feat")
+        _shape(target, (ng, ng), "target")
+        if loss_out is not None:
+            _shape(loss_out, (1,), "loss_out")
+        else:
             loss_out = torch.empty(1, dtype=torch.float32, device=feat.device)
         st = self.ctx.lib.gw_tail_train_step(self.ctx.handle, C.byref(self.mlp), C.byref(self.adam),
                                              _dev(feat, torch.float32, "feat"), _dev(target, torch.complex64, "target"),
@@ -579,8 +710,12 @@ class TailModel:
 
     def loss(self, feat, target, loss_out=None):
         import torch
-        ng = feat.shape[0]
-        if loss_out is None:
+        ng = _ndim(feat, 2, "feat")[0]
+        _shape(feat, (ng, 4), "feat")
+        _shape(target, (ng, ng), "target")
+        if loss_out is not None:
+            _shape(loss_out, (1,), "loss_out")
+        else:
             loss_out = torch.empty(1, dtype=torch.float32, device=feat.device)
         st = self.ctx.lib.gw_tail_loss(self.ctx.handle, C.byref(self.mlp), _dev(feat, torch.float32, "feat"),
                                        _dev(target, torch.complex64, "target"), ng,
@@ -591,8 +726,12 @@ class TailModel:
     def correct(self, p_trunc, feat, out=None):
         """Returns (p_corr, used_fallback); with the fallback p_corr is None."""
         import torch
-        ng = p_trunc.shape[0]
-        if out is None:
+        ng = _ndim(p_trunc, 2, "p_trunc")[0]
+        _shape(p_trunc, (ng, ng), "p_trunc")
+        _shape(feat, (ng, 4), "feat")
+        if out is not None:
+            _shape(out, (ng, ng), "p_corr")
+        else:
             out = torch.empty_like(p_trunc)
         fb = C.c_int(0)
         st = self.ctx.lib.gw_tail_correct(self.ctx.handle, C.byref(self.mlp), _dev(p_trunc, torch.complex64, "p_trunc"),
@@ -604,8 +743,12 @@ class TailModel:
 
 def tail_target(p_full, p_trunc, out=None, ctx: Optional[Context] = None):
     import torch
-    ng = p_full.shape[0]
-    if out is None:
+    ng = _ndim(p_full, 2, "p_full")[0]
+    _shape(p_full, (ng, ng), "p_full")
+    _shape(p_trunc, (ng, ng), "p_trunc")
+    if out is not None:
+        _shape(out, (ng, ng), "target")
+    else:
         out = torch.empty_like(p_full)
     ctx = ctx or context(p_full.device.index)
     st = ctx.lib.gw_tail_target(ctx.handle, _dev(p_full, torch.complex64, "p_full"),
@@ -617,10 +760,14 @@ def tail_target(p_full, p_trunc, out=None, ctx: Optional[Context] = None):
 
 def tail_features(p_gg, n, a_bohr, q, miller, nc, e_max, out=None, ctx: Optional[Context] = None):
     import torch
+    ng = _miller_rows(miller)
+    _len(q, 3, "q")
+    _shape(p_gg, (ng, ng), "p_gg")
     m, pm = _host_i32(miller, "g_miller")
-    ng = m.shape[0]
     qa, pq = _host_f64(q, "q")
-    if out is None:
+    if out is not None:
+        _shape(out, (ng, 4), "feat")
+    else:
         out = torch.empty((ng, 4), dtype=torch.float32, device=p_gg.device)
     ctx = ctx or context(p_gg.device.index)
     st = ctx.lib.gw_tail_features(ctx.handle, _dev(p_gg, torch.complex64, "p_gg"), ng, _grid(n, a_bohr), pq, pm,
