@@ -1,6 +1,7 @@
 """The Python binding checks every buffer's shape and every host array's length against the sizes
 it passes to the C ABI, before any device or library call (CPU tensors suffice: a mismatch raises
-ValueError, a consistent call gets as far as the device check and raises TypeError)."""
+ValueError; a consistent call passes the shape checks and fails later, at the device or context
+step, with another error)."""
 import numpy as np
 import pytest
 import torch
