@@ -302,6 +302,11 @@ typedef struct {
 int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const double *e_v, gw_grid grid,
                               int nq, const gw_qjob *jobs, const gw_opts *opts, double head, void *stream);
 
+/* Number of batched-q graphs this context has captured so far (a replay of a cached graph does not
+ * count; a call whose shapes, pointers, q, spheres, head or options differ from the cached graph's
+ * captures a new one).  0 for NULL or a context that never ran a batch. */
+int gw_graph_captures(const gw_ctx *ctx);
+
 /* ---------------------------------------------------------------------------
  * Tile autotuner of the rank-K update: times every tile of `precision` on the
  * first min(nv, 8) occupied bands of these inputs (same N_r and Nc) and caches

@@ -20,7 +20,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "split_bf16": 1, "fp16": 2, "split_fp16": 2}
 EXPORTS = ("gw_opts_default", "gw_version", "gw_status_string", "gw_create", "gw_destroy", "gw_last_error",
            "gw_workspace_bytes", "gw_tile_count", "gw_tile_name", "gw_default_tile", "gw_pair_products", "gw_polarizability_r",
            "gw_sphere_transform", "gw_polarizability", "gw_epsilon", "gw_eps_inverse", "gw_hpd_inverse",
-           "gw_polarizability_batched", "gw_autotune", "gw_tail_init", "gw_tail_target", "gw_tail_features",
+           "gw_polarizability_batched", "gw_graph_captures", "gw_autotune", "gw_tail_init", "gw_tail_target", "gw_tail_features",
            "gw_tail_forward", "gw_tail_train_step", "gw_tail_loss", "gw_tail_correct", "gw_newton_inverse",
            "gw_eps_inverse_newton", "gw_orbitals_to_grid",
            "gw_plasmon_pole", "gw_pp_eps_inverse", "gw_sigma_static", "gw_sigma_sex_modes", "gw_mfma_rate")
@@ -86,6 +86,7 @@ def load() -> C.CDLL:
         "gw_eps_inverse": (i, [vp, vp, i, Grid, vp, vp, d, vp, vp]),
         "gw_hpd_inverse": (i, [vp, vp, i, vp, vp]),
         "gw_polarizability_batched": (i, [vp, vp, i, vp, Grid, i, C.POINTER(QJob), C.POINTER(Opts), d, vp]),
+        "gw_graph_captures": (i, [vp]),
         "gw_autotune": (i, [vp, vp, i, vp, i, i, vp, vp, i, vp, C.POINTER(i), vp, vp]),
         "gw_tail_init": (i, [vp, C.POINTER(Mlp), vp, vp]),
         "gw_tail_target": (i, [vp, vp, vp, i, vp, vp]),
@@ -144,6 +145,11 @@ class Context:
     @property
     def workspace_bytes(self) -> int:
         return int(self.lib.gw_workspace_bytes(self.handle))
+
+    @property
+    def graph_captures(self) -> int:
+        """Batched-q graphs captured by this context so far (replays do not count)."""
+        return int(self.lib.gw_graph_captures(self.handle))
 
 
 _contexts: dict = {}

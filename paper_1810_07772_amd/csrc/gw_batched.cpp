@@ -82,6 +82,7 @@ struct Cached {
   std::vector<hipEvent_t> events;
   int *pivots_host = nullptr;
   int npiv = 0;
+  int captures = 0;                // graphs captured so far (a replay does not count)
 };
 
 Cached *cache_of(gw_ctx *ctx) {
@@ -192,6 +193,11 @@ int gw_autotune(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *psi_c, i
                        (float2 *)p_scratch, best_tile, times_ms, reinterpret_cast<hipStream_t>(stream));
 }
 
+int gw_graph_captures(const gw_ctx *ctx) {
+  if (!ctx || !ctx->graph_cache) return 0;
+  return static_cast<const Cached *>(ctx->graph_cache)->captures;
+}
+
 int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const double *e_v, gw_grid grid, int nq,
                               const gw_qjob *jobs, const gw_opts *opts, double head, void *stream) {
   GWX_STATUS(api_begin(ctx));
@@ -292,10 +298,17 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
   }
 
   // ---- graph key: everything baked into the captured launches ---------------------------------
+  // (field by field: the option and grid structs have padding bytes whose contents are undefined)
   uint64_t h = fnv(&nv, sizeof nv);
-  h = fnv(&grid, sizeof grid, h);
+  h = fnv(&grid.n1, sizeof grid.n1, h);
+  h = fnv(&grid.n2, sizeof grid.n2, h);
+  h = fnv(&grid.n3, sizeof grid.n3, h);
+  h = fnv(&grid.a_bohr, sizeof grid.a_bohr, h);
   h = fnv(&nq, sizeof nq, h);
-  h = fnv(&o, sizeof o, h);
+  h = fnv(&o.precision, sizeof o.precision, h);
+  h = fnv(&o.prefactor, sizeof o.prefactor, h);
+  h = fnv(&o.accumulate, sizeof o.accumulate, h);
+  h = fnv(&o.tile, sizeof o.tile, h);
   h = fnv(&head, sizeof head, h);
   h = fnv(&psi_occ, sizeof psi_occ, h);
   h = fnv(tiles.data(), tiles.size() * sizeof(int), h);
@@ -372,6 +385,7 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
     GWX_HIP(ctx, hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
     c->key = key;
     c->ptrs = ptrs;
+    ++c->captures;
   }
   if (c->npiv < nq) {
     if (c->pivots_host) (void)hipHostFree(c->pivots_host);

@@ -208,3 +208,9 @@ def test_package_does_not_import_oracle():
                     if isinstance(node, (ast.Import, ast.ImportFrom)):
                         mods = [a.name for a in node.names] if isinstance(node, ast.Import) else [node.module or ""]
                         assert not any(mm.split(".")[0] == "oracle" for mm in mods), f
+
+
+def test_graph_capture_counter_without_batches(gw):
+    lib = gw.load()
+    assert lib.gw_graph_captures(None) == 0
+    assert gw.Context(-1).graph_captures == 0

@@ -71,16 +71,20 @@ def test_batched_replay_reuses_graph_and_rereads_energies(gw):
     b = small_batch()
     pv = c64(b["psi_v"])
     jobs = jobs_for(b)
+    ctx = gw.context(pv.device.index)
     gw.polarizability_batched(pv, b["e_v"], b["n"], b["a_bohr"], jobs, precision="fp32", tile=4)
     first = [jb["p_gg"].clone() for jb in jobs]
+    captured = ctx.graph_captures
     gw.polarizability_batched(pv, b["e_v"], b["n"], b["a_bohr"], jobs, precision="fp32", tile=4)
     torch.cuda.synchronize()
+    assert ctx.graph_captures == captured, "an identical second call captured a new graph"
     for j, jb in enumerate(jobs):
         assert torch.equal(first[j], jb["p_gg"])
     # new energies through the same host arrays: the cached graph must see them
     b["jobs"][1]["e_c"] *= 1.5
     jobs[1]["e_c"] = b["jobs"][1]["e_c"]
     gw.polarizability_batched(pv, b["e_v"], b["n"], b["a_bohr"], jobs, precision="fp32", tile=4)
+    assert ctx.graph_captures == captured, "new energies alone must not capture a new graph"
     src = b["jobs"][1]
     single = gw.polarizability(pv, jobs[1]["psi_c"], b["e_v"], src["e_c"], b["n"], b["a_bohr"], src["q"], src["miller"],
                                precision="fp32", tile=4)
