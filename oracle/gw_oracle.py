@@ -31,7 +31,7 @@ import numpy as np
 __all__ = [
     "pair_products", "polarizability_r", "row_transform", "to_sphere", "coulomb_sqrt",
     "epsilon", "eps_inverse", "eps_inverse_cholesky", "newton_schulz_inverse", "adler_wiser",
-    "rel_f", "grid_phase_index", "adler_wiser_selected", "orbitals_on_grid",
+    "rel_f", "grid_phase_index", "adler_wiser_selected", "orbitals_on_grid", "to_sphere_factored",
 ]
 
 
@@ -223,3 +223,26 @@ def adler_wiser_selected(psi_v, psi_c, e_v, e_c, n: Sequence[int], miller_sel, p
         w = prefactor / (-de[v])
         out += (mm * w[:, None]).T @ np.conj(mm)
     return out
+
+
+def to_sphere_factored(a, b, n: Sequence[int], miller_rows, miller_cols=None) -> np.ndarray:
+    """Both transforms of Sec. 4.1 for a matrix given by factors, P(r, r') = sum_k a_k(r) conj(b_k(r'))
+    (a, b complex [R][N_r]), on selected sphere vectors:
+        P~(g, g') = sum_{r, r'} exp(-i G_g.r) P(r, r') exp(+i G_g'.r')
+                  = sum_k [sum_r exp(-i G_g.r) a_k(r)] conj[sum_r' exp(-i G_g'.r') b_k(r')],
+    with every grid sum written out directly (no FFT), for sizes where P itself is out of reach.
+    Rows g run over miller_rows, columns g' over miller_cols (default: the same list)."""
+    n = tuple(int(x) for x in n)
+    mc = miller_rows if miller_cols is None else miller_cols
+    i1, i2, i3 = np.meshgrid(*(np.arange(x) for x in n), indexing="ij")
+    i1, i2, i3 = i1.ravel(), i2.ravel(), i3.ravel()
+
+    def kernel(miller):                                   # exp(-i G_g.r) as [N_r][len(miller)]
+        m = np.asarray(miller, np.float64)
+        ph = (np.multiply.outer(i1, m[:, 0]) / n[0] + np.multiply.outer(i2, m[:, 1]) / n[1]
+              + np.multiply.outer(i3, m[:, 2]) / n[2])
+        return np.exp(-2j * np.pi * ph)
+
+    ah = np.asarray(a, np.complex128) @ kernel(miller_rows)     # [R][n_rows]
+    bh = np.asarray(b, np.complex128) @ kernel(mc)              # [R][n_cols]
+    return ah.T @ np.conj(bh)

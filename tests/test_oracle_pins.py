@@ -345,3 +345,35 @@ def test_orbitals_on_grid_orthonormal_and_equal_to_generator():
     psi = orc.orbitals_on_grid(s.coeff, s.pw_miller, s.n)
     assert np.max(np.abs(psi @ psi.conj().T - np.eye(16))) < 1e-13
     assert np.max(np.abs(psi[:4] - s.psi_v)) < 1e-14 and np.max(np.abs(psi[4:] - s.psi_c)) < 1e-14
+
+
+# --- both transforms of a factored P (sampled-entry route for large grids) --------------------
+def test_to_sphere_factored_plane_wave_closed_form():
+    """P(r,r') = exp(+i G_a.r) exp(-i G_b.r'): the two transforms of Sec. 4.1 give N_r^2 at (g, g') =
+    (a, b) and zero elsewhere.  Pins the exponent signs of both sides and the absence of any
+    normalisation, independently of the FFT route."""
+    n = (5, 4, 6)
+    nr = 120
+    mill = gs.sphere(n, r2=3.0, q=(0.1, 0.0, -0.2))
+    ia, ib = 4, 9
+    i1, i2, i3 = np.meshgrid(*(np.arange(x) for x in n), indexing="ij")
+    def pw(m):
+        return np.exp(2j * np.pi * (m[0] * i1 / n[0] + m[1] * i2 / n[1] + m[2] * i3 / n[2])).ravel()
+    pt = orc.to_sphere_factored(pw(mill[ia])[None, :], pw(mill[ib])[None, :], n, mill)
+    want = np.zeros((len(mill), len(mill)), dtype=np.complex128)
+    want[ia, ib] = nr * nr
+    assert np.max(np.abs(pt - want)) < 1e-9
+
+
+def test_to_sphere_factored_equals_dense_route():
+    """On a non-cubic grid with q != 0, the factored direct sums equal the FFT route applied to the dense
+    P = sum_k a_k b_k^H, on a rectangular block of rows and columns."""
+    n = (6, 5, 4)
+    rng = np.random.default_rng(31)
+    a = rng.standard_normal((3, 120)) + 1j * rng.standard_normal((3, 120))
+    b = rng.standard_normal((3, 120)) + 1j * rng.standard_normal((3, 120))
+    mill = gs.sphere(n, r2=4.0, q=(0.0, 0.3, 0.1))
+    dense = orc.to_sphere(a.T @ np.conj(b), n, mill)
+    rows, cols = np.array([0, 2, 5, len(mill) - 1]), np.array([1, 3, 4, 7, 11])
+    got = orc.to_sphere_factored(a, b, n, mill[rows], mill[cols])
+    assert np.max(np.abs(got - dense[np.ix_(rows, cols)])) < 1e-12 * np.max(np.abs(dense))
