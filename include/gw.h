@@ -150,6 +150,25 @@ int gw_polarizability_r(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *
                         void *stream);
 
 /* ---------------------------------------------------------------------------
+ * The same update as gw_polarizability_r, allocating nothing: for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Inputs, output, options and results
+ * are those of gw_polarizability_r, except that opts->tile = -1 means the default
+ * tile of the precision (no autotuner lookup).  The energies, the pair-scale table
+ * and the FP16 band exponents go to a fixed 8 MiB device array that each GPU holds
+ * for the life of the process (its address is resolved once per device by
+ * gw_create): calls needing more than 8 MiB, i.e. about
+ * 8 (nv + nc) + 4 nv ceil32(nc) (+ 4 (4 nv + nc) for FP16) bytes, return
+ * GW_E_INVAL with the figure in gw_last_error.  Every call on one GPU shares that
+ * array, so calls that overlap on one GPU (different streams or host threads)
+ * race; calls on one stream are ordered.  No hipMalloc, hipFree or other
+ * allocating call is made.
+ * ------------------------------------------------------------------------- */
+int gw_polarizability_r_noalloc(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *psi_c, int nc, int nr,
+                                const double *e_v, const double *e_c, const gw_opts *opts, gw_c32 *p_rr,
+                                void *stream);
+
+/* ---------------------------------------------------------------------------
  * Both transforms of Sec. 4.1 restricted to the sphere:
  *   p_gg[g][g'] = sum_{r,r'} exp(-i G_g.r) p_rr[r][r'] exp(+i G_g'.r').
  *   p_rr [nr][nr] complex64 (read only), g_miller host [ng][3], p_gg [ng][ng] complex64.

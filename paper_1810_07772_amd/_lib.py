@@ -19,6 +19,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "split_bf16": 1, "fp16": 2, "split_fp16": 2}
 # Every symbol include/gw.h declares.
 EXPORTS = ("gw_opts_default", "gw_version", "gw_status_string", "gw_create", "gw_destroy", "gw_last_error",
            "gw_workspace_bytes", "gw_tile_count", "gw_tile_name", "gw_default_tile", "gw_pair_products", "gw_polarizability_r",
+           "gw_polarizability_r_noalloc",
            "gw_sphere_transform", "gw_polarizability", "gw_epsilon", "gw_eps_inverse", "gw_hpd_inverse",
            "gw_polarizability_batched", "gw_graph_captures", "gw_autotune", "gw_tail_init", "gw_tail_target", "gw_tail_features",
            "gw_tail_forward", "gw_tail_train_step", "gw_tail_loss", "gw_tail_correct", "gw_newton_inverse",
@@ -80,6 +81,7 @@ def load() -> C.CDLL:
         "gw_default_tile": (i, [i, i]),
         "gw_pair_products": (i, [vp, vp, i, vp, i, i, vp, vp, d, vp, vp]),
         "gw_polarizability_r": (i, [vp, vp, i, vp, i, i, vp, vp, C.POINTER(Opts), vp, vp]),
+        "gw_polarizability_r_noalloc": (i, [vp, vp, i, vp, i, i, vp, vp, C.POINTER(Opts), vp, vp]),
         "gw_sphere_transform": (i, [vp, vp, Grid, vp, i, vp, vp]),
         "gw_polarizability": (i, [vp, vp, i, vp, i, vp, vp, Grid, vp, vp, i, C.POINTER(Opts), vp, vp, vp]),
         "gw_epsilon": (i, [vp, vp, i, Grid, vp, vp, d, vp, vp]),
@@ -321,6 +323,24 @@ def polarizability_r(psi_v, psi_c, e_v, e_c, precision="fp32", prefactor=1.0, ac
                                      _dev(psi_c, torch.complex64, "psi_c"), nc, nr, pev, pec, C.byref(o),
                                      _dev(out, torch.complex64, "p_rr"), _stream(psi_v))
     ctx.check(st, "gw_polarizability_r")
+    return out
+
+
+def polarizability_r_noalloc(psi_v, psi_c, e_v, e_c, out, precision="fp32", prefactor=1.0, accumulate=False, tile=-1,
+                             ctx: Optional[Context] = None):
+    """gw_polarizability_r_noalloc: the update into the caller's `out` [nr][nr], with the library's fixed
+    scratch array instead of any allocation (tile -1: the precision's default tile)."""
+    import torch
+    nv, nc, nr = _orbitals(psi_v, psi_c, e_v, e_c)
+    _shape(out, (nr, nr), "p_rr")
+    ctx = ctx or context(psi_v.device.index)
+    ev, pev = _host_f64(e_v, "e_v")
+    ec, pec = _host_f64(e_c, "e_c")
+    o = _opts(precision, prefactor, accumulate, tile)
+    st = ctx.lib.gw_polarizability_r_noalloc(ctx.handle, _dev(psi_v, torch.complex64, "psi_v"), nv,
+                                             _dev(psi_c, torch.complex64, "psi_c"), nc, nr, pev, pec, C.byref(o),
+                                             _dev(out, torch.complex64, "p_rr"), _stream(psi_v))
+    ctx.check(st, "gw_polarizability_r_noalloc")
     return out
 
 

@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("GW_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["gw_api.cpp", "gw_batched.cpp", "gw_tail.cpp", "gw_pp.cpp", "pp.hip", "gw_sigma.cpp", "sigma.hip", "pair.hip", "herk.hip", "fft.hip", "eps.hip", "chol.hip",
-           "tail.hip"]
+           "tail.hip", "noalloc.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions stay off (hipcc's host pass warns that it ignores this)

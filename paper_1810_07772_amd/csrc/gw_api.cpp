@@ -426,6 +426,13 @@ int gw_create(gw_ctx **ctx, int hip_device, size_t cap) {
       return GW_E_HIP;
     }
     *c->pivot_host = 0;
+    // the allocation-free update's scratch array: this device's address, resolved with the device current
+    if (gwi::noalloc_resolve(hip_device) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipHostFree(c->pivot_host);
+      delete c;
+      return GW_E_HIP;
+    }
   }
   *ctx = c;
   return GW_OK;

@@ -217,6 +217,12 @@ int api_begin(gw_ctx *ctx);
 void api_set_err(gw_ctx *ctx, const char *msg);
 int api_device(gw_ctx *ctx);
 
+// ---- allocation-free update (noalloc.hip) ------------------------------------------------------------
+// Resolve this device's address of the fixed scratch array (call with `device` current).
+hipError_t noalloc_resolve(int device);
+size_t noalloc_scratch_bytes(int nv, int nc, int precision);
+size_t noalloc_scratch_limit();
+
 // ---- tile autotuner --------------------------------------------------------------------------------
 // Tuned tile for (nr, nv, nc, precision) on the context's device, or -1 if none is cached.
 int tuned_tile(gw_ctx *ctx, int nr, int nv, int nc, int precision);
