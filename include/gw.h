@@ -178,10 +178,23 @@ int gw_polarizability_r_noalloc(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const 
 int gw_sphere_transform(gw_ctx *ctx, const gw_c32 *p_rr, gw_grid grid, const int *g_miller, int ng,
                         gw_c32 *p_gg, void *stream);
 
+/* The same transforms for a Hermitian P(r,r') (as gw_polarizability_r writes it): P~ is formed
+ * from P's upper triangle alone, P = M + M^H with M the strict upper triangle plus half the real
+ * diagonal, so only that half of p_rr is read; P~ = F M F^H + (F M F^H)^H.  Entries below the
+ * diagonal and the imaginary part of the diagonal are then ignored.  This form needs n2 = n3 (each
+ * row's i1 planes are transformed over (i2, i3) by one wave); on other grids the strided transform of
+ * the whole p_rr runs, so p_rr must hold both triangles.  Arguments as gw_sphere_transform. */
+int gw_sphere_transform_herm(gw_ctx *ctx, const gw_c32 *p_rr, gw_grid grid, const int *g_miller, int ng,
+                             gw_c32 *p_gg, void *stream);
+
 /* ---------------------------------------------------------------------------
  * The whole build from orbitals to P~(g,g') (a rank-K update then both transforms).
- *   psi_occ [nv][nr], psi_unocc [nc][nr] with nr = n1*n2*n3; q (host) [3] is
- *   accepted for the interface (q enters only the sphere and the Coulomb step).
+ *   psi_occ [nv][nr], psi_unocc [nc][nr] with nr = n1*n2*n3; q (host) [3] enters
+ *   only the sphere, the Coulomb step and the choice of transform: P is Hermitian, so
+ *   the transforms use its upper triangle (as gw_sphere_transform_herm) unless
+ *   accumulate is set or the sphere holds a vector with 0 < |q+m| < 0.01 (crystal
+ *   units), whose Coulomb weight would magnify that form's rounding of the head row;
+ *   then all of P is transformed.
  *   p_rr: [nr][nr] buffer that receives P(r,r'), or NULL to use workspace.
  *   p_gg: [ng][ng] complex64 output.
  * ------------------------------------------------------------------------- */
@@ -346,7 +359,8 @@ int gw_autotune(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *psi_c, i
  *   features x_G = (|q+G| [1/Bohr], log|Re P~_Nc(G,G)|, Nc/N_g, E_max [Ha]),
  *   o_G = MLP(x_G): 4 -> 128 -> 128 -> 33, SiLU, BF16 weights, FP32 arithmetic,
  *         inputs normalised by the stored mean and std,
- *   s_G = |Re P~_Nc(G,G)|, d_G = softplus(o_G0) s_G, u_Gk = (o_G,1+k + i o_G,17+k) sqrt(s_G),
+ *   s_G = |Re P~_Nc(G,G)|, d_G = softplus(o_G0) s_G, u_Gk = (o_G,1+k + i o_G,17+k) sqrt(s_G) for
+ *   k < rank (zero for k >= rank; rank <= 16 is a model setting, chosen on validation systems),
  *   dP~ = -(diag(d) + U U^H)  (negative semidefinite, like the missing tail),
  *   training loss ||dP~ - T||_F^2 / ||T||_F^2 with T = H(P~_4Nc) - H(P~_Nc), H(X) = (X + X^H)/2,
  *   minimised with Adam on an FP32 master copy of the parameters.
@@ -359,13 +373,15 @@ typedef struct {
   void *w;        /* device BF16 [GW_TAIL_NWEIGHT]: W1, W2, W3, each [inputs][outputs] row-major   */
   float *b;       /* device FP32 [GW_TAIL_NBIAS]: b1, b2, b3                                      */
   float *norm;    /* device FP32 [16]: feature mean[4], std[4], training box lo[4], hi[4] (raw)   */
+  int rank;       /* columns of U in use, 0..16 (0: diagonal correction only); outputs of the other */
+                  /* columns are ignored and receive no gradient                                    */
 } gw_mlp;
 
 typedef struct {
   float *master;  /* device FP32 [GW_TAIL_NPARAM] parameters (master copy)                        */
   float *m, *v;   /* device FP32 [GW_TAIL_NPARAM] Adam moments (zero-initialised by the caller)     */
   float *grad;    /* device FP32 [GW_TAIL_NPARAM] gradient of the last step (written)             */
-  int step;       /* steps taken so far; each train step increments it                            */
+  int step;       /* steps taken so far; each train step increments it (bias corrections 1 - beta^step) */
   float lr, beta1, beta2, eps;
 } gw_adam;
 
@@ -388,6 +404,32 @@ int gw_tail_forward(gw_ctx *ctx, const gw_mlp *w, const float *feat, int ng, flo
  * target [ng][ng] must be Hermitian (as gw_tail_target makes it). */
 int gw_tail_train_step(gw_ctx *ctx, gw_mlp *w, gw_adam *opt, const float *feat, const gw_c32 *target, int ng,
                        float *loss_out, void *stream);
+
+/* Training steps replayed from captured HIP graphs: step k trains on system j = order[k] exactly as
+ * gw_tail_train_step would (feats[j] [ngs[j]][4] and targets[j] [ngs[j]][ngs[j]] are device arrays;
+ * feats, targets, ngs and order are host arrays) and writes that step's loss to loss_out[j] (device
+ * FP32 [nsys]).  The launch sequence of one step on one system is captured once into a graph, cached
+ * in the context while the model, optimiser, system, workspace and hyperparameters stay the same, and
+ * launched once per step; the Adam step count is kept on the device inside the graphs.
+ * opt->step += nsteps.  Only kernels are captured (no memsets, no allocation). */
+int gw_tail_train_steps(gw_ctx *ctx, gw_mlp *w, gw_adam *opt, int nsys, const float *const *feats,
+                        const gw_c32 *const *targets, const int *ngs, int nsteps, const int *order, float *loss_out,
+                        void *stream);
+
+/* Number of training-step graphs cached in the context (0 for NULL). */
+int gw_tail_graph_count(const gw_ctx *ctx);
+
+/* Feature statistics of a training set into norm (device FP32 [16]): mean[4] and population std[4]
+ * (1 where a feature is constant to 1e-12 of max(1, |mean|)) over all rows of the nsys feature
+ * arrays feats[i] [ngs[i]][4] (device pointers in a host array), then the training box min[4],
+ * max[4].  Accumulated in FP64. */
+int gw_tail_fit_norm(gw_ctx *ctx, int nsys, const float *const *feats, const int *ngs, float *norm, void *stream);
+
+/* Parts of the training loss of the current weights on one system, into parts (device FP32 [4]):
+ * ||offdiag(dP~ - T)||_F^2, ||offdiag(T)||_F^2, ||diag(dP~ - T)||^2, ||diag(T)||^2, so that
+ * loss = (parts[0] + parts[2]) / (parts[1] + parts[3]).  Used to judge the rank on validation. */
+int gw_tail_residual_parts(gw_ctx *ctx, const gw_mlp *w, const float *feat, const gw_c32 *target, int ng, float *parts,
+                           void *stream);
 
 /* The training loss of the current weights on one system, into the device float *loss_out
  * (forward and loss only; no gradient, no update). */

@@ -7,9 +7,12 @@ truncation of Eq.(Pstatic) that the paper lists as its first technical issue):
   x_G      = (|q+G|, log|Re P~_{Nc}(G,G)|, Nc/N_g, E_max)   raw per-G features
   o_G      = MLP(normalise(x_G))                        4 -> 128 -> 128 -> 33, SiLU, BF16 weights
   s_G      = |Re P~_{Nc}(G,G)|
-  d_G      = softplus(o_G0) s_G,   u_Gk = (o_G,1+k + i o_G,17+k) sqrt(s_G),  k < 16
+  d_G      = softplus(o_G0) s_G,   u_Gk = (o_G,1+k + i o_G,17+k) sqrt(s_G),  k < r (r <= 16; 0 beyond)
   dP~      = -(diag(d) + U U^H)                          negative semidefinite by construction
   loss     = ||dP~ - T||_F^2 / ||T||_F^2
+
+The rank r of the U U^H term is a model setting (16 at most, chosen on validation systems); with r = 0
+the correction is diagonal.
 
 Every function here is the plain definition in float64 (dense N_g x N_g matrices where the
 definition has them); the gradients are the analytic chain rule, pinned by central finite
@@ -69,28 +72,38 @@ def forward(x, params, mean, std):
     return o, dict(xn=xn, z1=z1, h1=h1, z2=z2, h2=h2)
 
 
-def head(o, s):
+def head(o, s, rank=RANK):
     d = softplus(o[:, 0]) * s
     u = (o[:, 1:1 + RANK] + 1j * o[:, 1 + RANK:1 + 2 * RANK]) * np.sqrt(s)[:, None]
+    u[:, rank:] = 0.0
     return d, u
 
 
-def correction(o, s):
-    d, u = head(o, s)
+def correction(o, s, rank=RANK):
+    d, u = head(o, s, rank)
     return -(np.diag(d) + u @ np.conj(u).T)
 
 
-def loss(o, s, target):
+def loss(o, s, target, rank=RANK):
     """||dP~ - T||_F^2 / ||T||_F^2 with the dense correction."""
     t = np.asarray(target, np.complex128)
-    r = correction(o, s) - t
+    r = correction(o, s, rank) - t
     return float(np.vdot(r, r).real / np.vdot(t, t).real)
 
 
-def loss_grad_o(o, s, target):
+def residual_parts(o, s, target, rank=RANK):
+    """(||offdiag(dP~ - T)||^2, ||offdiag T||^2, ||diag(dP~ - T)||^2, ||diag T||^2) with the dense correction."""
+    t = np.asarray(target, np.complex128)
+    r = correction(o, s, rank) - t
+    off = ~np.eye(len(t), dtype=bool)
+    sq = lambda x: float((np.abs(x) ** 2).sum())
+    return sq(r[off]), sq(t[off]), sq(np.diag(r)), sq(np.diag(t))
+
+
+def loss_grad_o(o, s, target, rank=RANK):
     """d loss / d o  [N_g][33] by the chain rule through the head (dense B = diag(d) + U U^H + T)."""
     t = np.asarray(target, np.complex128)
-    d, u = head(o, s)
+    d, u = head(o, s, rank)
     b = np.diag(d) + u @ np.conj(u).T + t
     tn = np.vdot(t, t).real
     bu = b @ u
@@ -99,6 +112,8 @@ def loss_grad_o(o, s, target):
     g[:, 0] = 2.0 * np.real(np.diag(b)) * sig * s / tn
     g[:, 1:1 + RANK] = 4.0 * np.real(bu) * np.sqrt(s)[:, None] / tn
     g[:, 1 + RANK:] = 4.0 * np.imag(bu) * np.sqrt(s)[:, None] / tn
+    g[:, 1 + rank:1 + RANK] = 0.0                  # outputs of unused U columns do not enter the loss
+    g[:, 1 + RANK + rank:] = 0.0
     return g
 
 
@@ -129,6 +144,17 @@ def unflatten(v) -> dict:
         out[k] = np.asarray(v[i:i + n], np.float64).reshape(shp)
         i += n
     return out
+
+
+def fit_norm(feats) -> np.ndarray:
+    """Feature statistics of a training set: mean and (population) std of every raw feature over all rows
+    of all systems (std 1 where a feature is constant to 1e-12 of max(1, |mean|)), then the training box
+    [min, max] of each feature; float32 [16]."""
+    x = np.concatenate([np.asarray(f, np.float64) for f in feats], axis=0)
+    mean = x.mean(axis=0)
+    std = np.sqrt(((x - mean) ** 2).mean(axis=0))
+    std[std <= 1e-12 * np.maximum(1.0, np.abs(mean))] = 1.0
+    return np.concatenate([mean, std, x.min(axis=0), x.max(axis=0)]).astype(np.float32)
 
 
 def adam(master, m, v, grad, step, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -20,9 +20,10 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "split_bf16": 1, "fp16": 2, "split_fp16": 2}
 EXPORTS = ("gw_opts_default", "gw_version", "gw_status_string", "gw_create", "gw_destroy", "gw_last_error",
            "gw_workspace_bytes", "gw_tile_count", "gw_tile_name", "gw_default_tile", "gw_pair_products", "gw_polarizability_r",
            "gw_polarizability_r_noalloc",
-           "gw_sphere_transform", "gw_polarizability", "gw_epsilon", "gw_eps_inverse", "gw_hpd_inverse",
+           "gw_sphere_transform", "gw_sphere_transform_herm", "gw_polarizability", "gw_epsilon", "gw_eps_inverse", "gw_hpd_inverse",
            "gw_polarizability_batched", "gw_graph_captures", "gw_autotune", "gw_tail_init", "gw_tail_target", "gw_tail_features",
-           "gw_tail_forward", "gw_tail_train_step", "gw_tail_loss", "gw_tail_correct", "gw_newton_inverse",
+           "gw_tail_forward", "gw_tail_train_step", "gw_tail_train_steps", "gw_tail_graph_count", "gw_tail_fit_norm",
+           "gw_tail_residual_parts", "gw_tail_loss", "gw_tail_correct", "gw_newton_inverse",
            "gw_eps_inverse_newton", "gw_orbitals_to_grid",
            "gw_plasmon_pole", "gw_pp_eps_inverse", "gw_sigma_static", "gw_sigma_sex_modes", "gw_mfma_rate")
 TAIL_NWEIGHT, TAIL_NBIAS, TAIL_NPARAM = 21120, 289, 21409
@@ -43,7 +44,7 @@ class Grid(C.Structure):
 
 
 class Mlp(C.Structure):
-    _fields_ = [("w", C.c_void_p), ("b", C.c_void_p), ("norm", C.c_void_p)]
+    _fields_ = [("w", C.c_void_p), ("b", C.c_void_p), ("norm", C.c_void_p), ("rank", C.c_int)]
 
 
 class Adam(C.Structure):
@@ -83,6 +84,7 @@ def load() -> C.CDLL:
         "gw_polarizability_r": (i, [vp, vp, i, vp, i, i, vp, vp, C.POINTER(Opts), vp, vp]),
         "gw_polarizability_r_noalloc": (i, [vp, vp, i, vp, i, i, vp, vp, C.POINTER(Opts), vp, vp]),
         "gw_sphere_transform": (i, [vp, vp, Grid, vp, i, vp, vp]),
+        "gw_sphere_transform_herm": (i, [vp, vp, Grid, vp, i, vp, vp]),
         "gw_polarizability": (i, [vp, vp, i, vp, i, vp, vp, Grid, vp, vp, i, C.POINTER(Opts), vp, vp, vp]),
         "gw_epsilon": (i, [vp, vp, i, Grid, vp, vp, d, vp, vp]),
         "gw_eps_inverse": (i, [vp, vp, i, Grid, vp, vp, d, vp, vp]),
@@ -97,6 +99,10 @@ def load() -> C.CDLL:
         "gw_tail_train_step": (i, [vp, C.POINTER(Mlp), C.POINTER(Adam), vp, vp, i, vp, vp]),
         "gw_tail_correct": (i, [vp, C.POINTER(Mlp), vp, i, vp, vp, C.POINTER(i), vp]),
         "gw_tail_loss": (i, [vp, C.POINTER(Mlp), vp, vp, i, vp, vp]),
+        "gw_tail_train_steps": (i, [vp, C.POINTER(Mlp), C.POINTER(Adam), i, vp, vp, vp, i, vp, vp, vp]),
+        "gw_tail_graph_count": (i, [vp]),
+        "gw_tail_fit_norm": (i, [vp, i, vp, vp, vp, vp]),
+        "gw_tail_residual_parts": (i, [vp, C.POINTER(Mlp), vp, vp, i, vp, vp]),
         "gw_plasmon_pole": (i, [vp, vp, i, Grid, vp, vp, vp, i, d, i, d, i, vp, vp, vp, C.POINTER(i),
                                 C.POINTER(d), vp]),
         "gw_pp_eps_inverse": (i, [vp, vp, i, Grid, vp, vp, vp, vp, vp, i, vp, i, vp, vp]),
@@ -344,7 +350,9 @@ def polarizability_r_noalloc(psi_v, psi_c, e_v, e_c, out, precision="fp32", pref
     return out
 
 
-def sphere_transform(p_rr, n, miller, out=None, ctx: Optional[Context] = None):
+def sphere_transform(p_rr, n, miller, out=None, hermitian=False, ctx: Optional[Context] = None):
+    """P~ on the sphere from P(r,r'); hermitian=True calls gw_sphere_transform_herm, which reads only the
+    upper triangle of a Hermitian P."""
     import torch
     nr = _nr_of(n)
     ng = _miller_rows(miller)
@@ -355,9 +363,10 @@ def sphere_transform(p_rr, n, miller, out=None, ctx: Optional[Context] = None):
     else:
         out = torch.empty((ng, ng), dtype=torch.complex64, device=p_rr.device)
     ctx = ctx or context(p_rr.device.index)
-    st = ctx.lib.gw_sphere_transform(ctx.handle, _dev(p_rr, torch.complex64, "p_rr"), _grid(n, 1.0), pm, ng,
-                                     _dev(out, torch.complex64, "p_gg"), _stream(p_rr))
-    ctx.check(st, "gw_sphere_transform")
+    fn = ctx.lib.gw_sphere_transform_herm if hermitian else ctx.lib.gw_sphere_transform
+    st = fn(ctx.handle, _dev(p_rr, torch.complex64, "p_rr"), _grid(n, 1.0), pm, ng, _dev(out, torch.complex64, "p_gg"),
+            _stream(p_rr))
+    ctx.check(st, "gw_sphere_transform_herm" if hermitian else "gw_sphere_transform")
     return out
 
 
@@ -682,14 +691,18 @@ class TailModel:
     """Device state of the band-tail MLP: BF16 weights, FP32 biases, feature normalisation and
     training box, and the Adam state on an FP32 master copy."""
 
-    def __init__(self, master, norm, device="cuda:0", lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+    def __init__(self, master, norm, device="cuda:0", lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, rank=16,
                  ctx: Optional[Context] = None):
         import torch
         dev = torch.device(device)
         self.ctx = ctx or context(dev.index if dev.index is not None else 0)
         self.w = torch.empty(TAIL_NWEIGHT, dtype=torch.bfloat16, device=dev)
         self.b = torch.empty(TAIL_NBIAS, dtype=torch.float32, device=dev)
-        self.norm = torch.as_tensor(np.asarray(norm, np.float32)).to(dev).contiguous()
+        if isinstance(norm, torch.Tensor):
+            _shape(norm, (16,), "norm")
+            self.norm = norm.to(device=dev, dtype=torch.float32).contiguous()
+        else:
+            self.norm = torch.as_tensor(np.asarray(norm, np.float32)).to(dev).contiguous()
         self.master = torch.as_tensor(np.asarray(master, np.float32)).to(dev).contiguous()
         self.m = torch.zeros(TAIL_NPARAM, dtype=torch.float32, device=dev)
         self.v = torch.zeros(TAIL_NPARAM, dtype=torch.float32, device=dev)
@@ -697,7 +710,7 @@ class TailModel:
         self.adam = Adam(C.c_void_p(self.master.data_ptr()), C.c_void_p(self.m.data_ptr()),
                          C.c_void_p(self.v.data_ptr()), C.c_void_p(self.grad.data_ptr()), 0, lr, beta1, beta2, eps)
         self.mlp = Mlp(C.c_void_p(self.w.data_ptr()), C.c_void_p(self.b.data_ptr()),
-                       C.c_void_p(self.norm.data_ptr()))
+                       C.c_void_p(self.norm.data_ptr()), int(rank))
         st = self.ctx.lib.gw_tail_init(self.ctx.handle, C.byref(self.mlp), C.c_void_p(self.master.data_ptr()),
                                        _stream(self.master))
         self.ctx.check(st, "gw_tail_init")
@@ -705,6 +718,58 @@ class TailModel:
     @property
     def step(self):
         return self.adam.step
+
+    @property
+    def rank(self):
+        return self.mlp.rank
+
+    @rank.setter
+    def rank(self, r):
+        if not 0 <= int(r) <= 16:
+            raise ValueError("rank must be in [0, 16]")
+        self.mlp.rank = int(r)
+
+    def train_steps(self, feats, targets, order, losses):
+        """gw_tail_train_steps: one graph-replayed step per entry of `order` (indices into feats/targets);
+        losses (device float32 [len(feats)]) receives each step's loss at its system's index."""
+        import torch
+        nsys = len(feats)
+        if len(targets) != nsys:
+            raise ValueError("feats and targets differ in length")
+        _shape(losses, (nsys,), "losses")
+        ngs = np.zeros(nsys, np.int32)
+        for j in range(nsys):
+            ng = _ndim(feats[j], 2, f"feats[{j}]")[0]
+            _shape(feats[j], (ng, 4), f"feats[{j}]")
+            _shape(targets[j], (ng, ng), f"targets[{j}]")
+            ngs[j] = ng
+        order = np.ascontiguousarray(np.asarray(order, np.int64).astype(np.int32))
+        if order.size and (order.min() < 0 or order.max() >= nsys):
+            raise ValueError("order entries must index the systems")
+        fp = (C.c_void_p * nsys)(*[_dev(f, torch.float32, "feat").value for f in feats])
+        tp = (C.c_void_p * nsys)(*[_dev(t, torch.complex64, "target").value for t in targets])
+        st = self.ctx.lib.gw_tail_train_steps(self.ctx.handle, C.byref(self.mlp), C.byref(self.adam), nsys, fp, tp,
+                                              ngs.ctypes.data_as(C.c_void_p), int(order.size),
+                                              order.ctypes.data_as(C.c_void_p),
+                                              _dev(losses, torch.float32, "losses"), _stream(losses))
+        self.ctx.check(st, "gw_tail_train_steps")
+        return losses
+
+    def residual_parts(self, feat, target, out=None):
+        """(||offdiag(dP~ - T)||^2, ||offdiag T||^2, ||diag(dP~ - T)||^2, ||diag T||^2) as a device float32 [4]."""
+        import torch
+        ng = _ndim(feat, 2, "feat")[0]
+        _shape(feat, (ng, 4), "feat")
+        _shape(target, (ng, ng), "target")
+        if out is not None:
+            _shape(out, (4,), "parts")
+        else:
+            out = torch.empty(4, dtype=torch.float32, device=feat.device)
+        st = self.ctx.lib.gw_tail_residual_parts(self.ctx.handle, C.byref(self.mlp), _dev(feat, torch.float32, "feat"),
+                                                 _dev(target, torch.complex64, "target"), ng,
+                                                 _dev(out, torch.float32, "parts"), _stream(feat))
+        self.ctx.check(st, "gw_tail_residual_parts")
+        return out
 
     def forward(self, feat, out=None):
         import torch
@@ -765,6 +830,30 @@ class TailModel:
                                           C.byref(fb), _stream(p_trunc))
         self.ctx.check(st, "gw_tail_correct")
         return (None, True) if fb.value else (out, False)
+
+
+def tail_fit_norm(feats, out=None, ctx: Optional[Context] = None):
+    """gw_tail_fit_norm: mean, std, min and max of the raw features over all rows of `feats` (device
+    float32 [ng_i][4] each), as a device float32 [16]."""
+    import torch
+    nsys = len(feats)
+    if nsys == 0:
+        raise ValueError("no feature arrays")
+    ngs = np.zeros(nsys, np.int32)
+    for j, f in enumerate(feats):
+        ng = _ndim(f, 2, f"feats[{j}]")[0]
+        _shape(f, (ng, 4), f"feats[{j}]")
+        ngs[j] = ng
+    if out is not None:
+        _shape(out, (16,), "norm")
+    else:
+        out = torch.empty(16, dtype=torch.float32, device=feats[0].device)
+    ctx = ctx or context(feats[0].device.index)
+    fp = (C.c_void_p * nsys)(*[_dev(f, torch.float32, "feat").value for f in feats])
+    st = ctx.lib.gw_tail_fit_norm(ctx.handle, nsys, fp, ngs.ctypes.data_as(C.c_void_p),
+                                  _dev(out, torch.float32, "norm"), _stream(feats[0]))
+    ctx.check(st, "gw_tail_fit_norm")
+    return out
 
 
 def tail_target(p_full, p_trunc, out=None, ctx: Optional[Context] = None):

@@ -504,9 +504,26 @@ size_t chol_small_bytes(int n) {
 #define GW_TRY(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
 
 hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small, int *pivot_dev, double2 *out,
-                       hipStream_t s) {
+                       hipStream_t s, hipStream_t side, hipEvent_t ev_fork, hipEvent_t ev_side) {
   const size_t nn = (size_t)n * n;
   const unsigned fill_blocks = (unsigned)((nn + 255) / 256);
+  // Look-ahead (when a second stream is given): after each panel, this stream applies the panel's
+  // update only to the next panel's columns (or rows) and goes on with the latency-bound chain of the
+  // next panel, while `side` applies it to everything beyond.  Before its next look-ahead product this
+  // stream waits for the side product, which writes the region that product reads and writes.
+  const bool la = side != nullptr && ev_fork != nullptr && ev_side != nullptr;
+  bool pending = false;                          // a side product is in flight
+  auto join = [&]() -> hipError_t {
+    if (!pending) return hipSuccess;
+    pending = false;
+    return hipStreamWaitEvent(s, ev_side, 0);
+  };
+  auto fork = [&]() -> hipError_t {
+    GW_TRY(hipEventRecord(ev_fork, s));
+    GW_TRY(hipStreamWaitEvent(side, ev_fork, 0));
+    pending = true;
+    return hipSuccess;
+  };
   GW_TRY(launch_fill_int(pivot_dev, 0, s));
   hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, l, n, 0.0);
   GW_TRY(hipGetLastError());
@@ -537,9 +554,25 @@ hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small
     const int rest = n - p1;
     if (rest > 0) {
       const double2 *lp = l + (size_t)p1 * n + p0;
-      GW_TRY(zgemm(rest, rest, p1 - p0, lp, n, 0, lp, n, 1, a + (size_t)p1 * n + p1, n, -1.0, 1.0, 1, 0, s));
+      if (!la) {
+        GW_TRY(zgemm(rest, rest, p1 - p0, lp, n, 0, lp, n, 1, a + (size_t)p1 * n + p1, n, -1.0, 1.0, 1, 0, s));
+      } else {
+        const int p2 = min(n, p1 + PW);
+        GW_TRY(join());
+        // the next panel's columns here: A[p1:, p1:p2] (lower part)
+        GW_TRY(zgemm(rest, p2 - p1, p1 - p0, lp, n, 0, lp, n, 1, a + (size_t)p1 * n + p1, n, -1.0, 1.0, 1, 0, s));
+        if (p2 < n) {
+          // everything beyond on the side stream: A[p2:, p2:]
+          const double2 *lq = l + (size_t)p2 * n + p0;
+          GW_TRY(fork());
+          GW_TRY(zgemm(n - p2, n - p2, p1 - p0, lq, n, 0, lq, n, 1, a + (size_t)p2 * n + p2, n, -1.0, 1.0, 1, 0,
+                       side));
+          GW_TRY(hipEventRecord(ev_side, side));
+        }
+      }
     }
   }
+  GW_TRY(join());
   // 2. X = L^-1 by right-looking block substitution on B = I (B reuses a)
   hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, a, n, 1.0);
   GW_TRY(hipGetLastError());
@@ -553,10 +586,27 @@ hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small
     GW_TRY(hipGetLastError());
     // below the panel: B[p1:, :p1] -= L[p1:, p0:p1] X[p0:p1, :p1]
     const int rest = n - p1;
-    if (rest > 0)
-      GW_TRY(zgemm(rest, p1, p1 - p0, l + (size_t)p1 * n + p0, n, 0, x + (size_t)p0 * n, n, 0, a + (size_t)p1 * n, n,
-                   -1.0, 1.0, 0, 0, s));
+    if (rest > 0) {
+      if (!la) {
+        GW_TRY(zgemm(rest, p1, p1 - p0, l + (size_t)p1 * n + p0, n, 0, x + (size_t)p0 * n, n, 0, a + (size_t)p1 * n,
+                     n, -1.0, 1.0, 0, 0, s));
+      } else {
+        const int p2 = min(n, p1 + PW);
+        GW_TRY(join());
+        // the next panel's rows here: B[p1:p2, :p1]
+        GW_TRY(zgemm(p2 - p1, p1, p1 - p0, l + (size_t)p1 * n + p0, n, 0, x + (size_t)p0 * n, n, 0,
+                     a + (size_t)p1 * n, n, -1.0, 1.0, 0, 0, s));
+        if (p2 < n) {
+          // the rows beyond on the side stream: B[p2:, :p1]
+          GW_TRY(fork());
+          GW_TRY(zgemm(n - p2, p1, p1 - p0, l + (size_t)p2 * n + p0, n, 0, x + (size_t)p0 * n, n, 0,
+                       a + (size_t)p2 * n, n, -1.0, 1.0, 0, 0, side));
+          GW_TRY(hipEventRecord(ev_side, side));
+        }
+      }
+    }
   }
+  GW_TRY(join());
   // 3. out = X^H X (lower tiles, k from max(row, col) since X is lower triangular), then mirror
   GW_TRY(zgemm(n, n, n, x, n, 1, x, n, 0, out, n, 1.0, 0.0, 1, 1, s));
   dim3 mg((n + 31) / 32, (n + 31) / 32);

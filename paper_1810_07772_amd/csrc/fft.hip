@@ -143,6 +143,38 @@ __device__ __forceinline__ void dft_regs(const float2 (&x)[N], float2 (&X)[N]) {
     }
 }
 
+// The same DFT with its inputs read through ld(n) one first-stage group at a time: the R1 inputs
+// x[R2 n1 + n2] of one n2 are loaded, combined and dropped before the next group's loads, so at most
+// R1 inputs and the N partial results are live (the plain form keeps all N inputs as well).
+template <int N, int SIGN, typename Load>
+__device__ __forceinline__ void dft_regs_load(Load ld, float2 (&X)[N]) {
+  constexpr int R1 = Factor<N>::R1, R2 = Factor<N>::R2;
+  float2 y[R1][R2];
+#pragma unroll
+  for (int n2 = 0; n2 < R2; ++n2) {
+    float2 xs[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) xs[n1] = ld(R2 * n1 + n2);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) cmac_tw<N, SIGN>(acc, xs[n1], (n1 * k1 % R1) * R2);
+      y[k1][n2] = (n2 * k1 == 0) ? acc : mul_tw<N, SIGN>(acc, n2 * k1);
+    }
+    if (n2 + 1 < R2) __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) cmac_tw<N, SIGN>(acc, y[k1][n2], (n2 * k2 % R2) * R1);
+      X[k1 + R1 * k2] = acc;
+    }
+}
+
 constexpr int FFT_THREADS = 256;
 
 // grid.x: batch blocks of 256, grid.y: flattened (o, u).
@@ -325,6 +357,185 @@ hipError_t launch_fft_gather_pass_t(int n, int sign, const float2 *in, float2 *o
 #undef GW_CASE
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// ---- the row-contiguous form of the two transforms ---------------------------------------------
+// With M a matrix whose rows are transformed along their contiguous index,
+//   Y[r][g'] = sum_r' M(r, r') exp(+i G_g'.r'),   r' = (i1 n2 + i2) n3 + i3,
+// every 3-D transform reads one contiguous row.  The i1 plane of a row (n2 x n3 consecutive values) is
+// transformed over i3 and i2 by one wave (plane_ab_kernel), keeping only the (k2, k3) pairs of the
+// sphere; plane_c_kernel then transforms over i1 and writes the sphere vectors in their order.  For a
+// Hermitian P (P = M + M^H with M its upper triangle and half its real diagonal), only the upper
+// triangle is read (HERM): planes wholly left of the diagonal are skipped and read as zero.
+
+// One wave per (row r, plane i1); four waves per workgroup.  Lane i3 (< N) loads the plane's column i3
+// (N consecutive loads of N consecutive values: each load instruction reads 8 N contiguous bytes),
+// transforms it over i2 in registers, and leaves its N outputs k2 in the wave's LDS block [k2][i3].
+// Lane s (< nk2) then takes the row k2 = k2list[s], transforms it over i3 in registers, and stores the
+// outputs whose (k2, k3) is a sphere pair at that pair's slot; the wave finally writes the npair slots
+// to y1[r][i1][.] with contiguous stores.  One wave reads and writes its own LDS block only, in program
+// order, so no workgroup barrier is needed.
+template <int N, bool HERM>
+__global__ __launch_bounds__(256) void plane_ab_kernel(const float2 *__restrict__ P, long long ldp, int nr, int n1,
+                                                       const int *__restrict__ k2list, int nk2,
+                                                       const int *__restrict__ mapab, int npair,
+                                                       float2 *__restrict__ y1) {
+  __shared__ float2 lds[4][N * N];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + w, i1 = blockIdx.y;
+  constexpr int PL = N * N;
+  if (r >= nr) return;
+  const long long c0 = (long long)i1 * PL;
+  if (HERM && c0 + PL <= r) return;              // left of the diagonal: zero, never read downstream
+  float2 *L = lds[w];
+  if (lane < N) {
+    const float2 *src = P + (long long)r * ldp + c0 + lane;
+    float2 x[N], X[N];
+#pragma unroll
+    for (int i2 = 0; i2 < N; ++i2) {
+      float2 v = src[i2 * N];
+      if (HERM) {
+        const long long c = c0 + i2 * N + lane;
+        if (c < r) v = make_float2(0.f, 0.f);
+        else if (c == r) v = make_float2(0.5f * v.x, 0.f);     // M carries half the (real) diagonal
+      }
+      x[i2] = v;
+    }
+    dft_regs<N, 1>(x, X);
+#pragma unroll
+    for (int k2 = 0; k2 < N; ++k2) L[k2 * N + lane] = X[k2];
+  }
+  if (lane < nk2) {
+    const int k2 = k2list[lane];
+    float2 x[N], X[N];
+#pragma unroll
+    for (int i3 = 0; i3 < N; ++i3) x[i3] = L[k2 * N + i3];
+    dft_regs<N, 1>(x, X);
+    const int *mrow = mapab + lane * N;
+#pragma unroll
+    for (int k3 = 0; k3 < N; ++k3) {
+      const int pid = mrow[k3];
+      if (pid >= 0) L[pid] = X[k3];                           // after every lane's reads (program order)
+    }
+  }
+  float2 *dst = y1 + ((long long)r * n1 + i1) * npair;
+  for (int j = lane; j < npair; j += 64) dst[j] = L[j];
+}
+
+// One workgroup per row r: the i1 transform of every pair (lanes over pairs, loads contiguous across
+// lanes), each output k1 sent to its sphere vector through mapct [N1][npair] (-1: not on the sphere).
+// The row's ng outputs are staged in LDS and written contiguously when they fit (STAGE), else directly.
+constexpr int PLANE_C_STAGE = 8192;   // sphere vectors staged in LDS (64 KB)
+template <int N1, bool HERM, bool STAGE>
+__global__ __launch_bounds__(256, 2) void plane_c_kernel(const float2 *__restrict__ y1, int plane, int npair,
+                                                      const int *__restrict__ mapct, int ng,
+                                                      float2 *__restrict__ y, long long ldy) {
+  extern __shared__ float2 so[];
+  const int r = blockIdx.x;
+  const int i1s = HERM ? r / plane : 0;          // planes left of the diagonal are zero
+  const float2 *src = y1 + (long long)r * N1 * npair;
+  float2 *yr = y + (long long)r * ldy;
+#pragma unroll 1
+  for (int p = threadIdx.x; p < npair; p += 256) {
+    float2 X[N1];
+    const float2 *sp = src + p;
+    dft_regs_load<N1, 1>([&](int i1) { return i1 >= i1s ? sp[(long long)i1 * npair] : make_float2(0.f, 0.f); }, X);
+    // outputs in groups of six map reads: a scheduling barrier between groups keeps the compiler from
+    // issuing every map read at once (N1 more live registers, and spills at N1 = 36 and 48)
+#pragma unroll
+    for (int kc = 0; kc < N1; kc += 6) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k1 = kc; k1 < (kc + 6 < N1 ? kc + 6 : N1); ++k1) {
+        const int g = mapct[k1 * npair + p];
+        if (g >= 0) {
+          if (STAGE) so[g] = X[k1];
+          else yr[g] = X[k1];
+        }
+      }
+    }
+  }
+  if (STAGE) {
+    __syncthreads();
+    for (int g = threadIdx.x; g < ng; g += 256) yr[g] = so[g];
+  }
+}
+
+// out = x + x^H for an [n][n] matrix (32 x 32 tiles, the transposed partner through LDS).
+__global__ __launch_bounds__(256) void add_adjoint_kernel(const float2 *__restrict__ x, int n, float2 *__restrict__ out) {
+  __shared__ float2 t[32][33];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = 0; k < 32; k += 8) {
+    const int r = c0 + ty + k, c = r0 + tx;
+    if (r < n && c < n) t[ty + k][tx] = x[(size_t)r * n + c];
+  }
+  __syncthreads();
+  for (int k = 0; k < 32; k += 8) {
+    const int g = r0 + ty + k, gp = c0 + tx;
+    if (g < n && gp < n) {
+      const float2 a = x[(size_t)g * n + gp], b = t[tx][ty + k];
+      out[(size_t)g * n + gp] = make_float2(a.x + b.x, a.y - b.y);
+    }
+  }
+}
+
+bool plane_path_supported(int n2, int n3) { return n2 == n3 && n3 <= 64 && fft_size_supported(n3); }
+
+hipError_t launch_plane_ab(int n, bool herm, const float2 *p, long long ldp, int nr, int n1, const int *k2list, int nk2,
+                           const int *mapab, int npair, float2 *y1, hipStream_t s) {
+  if (n1 > 65535 || nk2 > 64 || nk2 > n) return hipErrorInvalidValue;
+  dim3 grid((nr + 3) / 4, n1), block(256);
+  switch (n) {
+#define GW_CASE(n_)                                                                                               \
+  case n_:                                                                                                        \
+    if (herm)                                                                                                     \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(plane_ab_kernel<n_, true>), grid, block, 0, s, p, ldp, nr, n1, k2list, nk2, \
+                         mapab, npair, y1);                                                                      \
+    else                                                                                                          \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(plane_ab_kernel<n_, false>), grid, block, 0, s, p, ldp, nr, n1, k2list, nk2, \
+                         mapab, npair, y1);                                                                      \
+    break;
+    GW_FFT_SIZES(GW_CASE)
+#undef GW_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_c(int n1, bool herm, const float2 *y1, int nr, int plane, int npair, const int *mapct, int ng,
+                          float2 *y, long long ldy, hipStream_t s) {
+  const bool stage = ng <= PLANE_C_STAGE;
+  const size_t shm = stage ? (size_t)ng * sizeof(float2) : 0;
+  dim3 grid(nr), block(256);
+  switch (n1) {
+#define GW_CASE(n_)                                                                                              \
+  case n_:                                                                                                       \
+    if (herm && stage)                                                                                           \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(plane_c_kernel<n_, true, true>), grid, block, shm, s, y1, plane, npair,  \
+                         mapct, ng, y, ldy);                                                                     \
+    else if (herm)                                                                                               \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(plane_c_kernel<n_, true, false>), grid, block, 0, s, y1, plane, npair,   \
+                         mapct, ng, y, ldy);                                                                     \
+    else if (stage)                                                                                              \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(plane_c_kernel<n_, false, true>), grid, block, shm, s, y1, plane, npair, \
+                         mapct, ng, y, ldy);                                                                     \
+    else                                                                                                         \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(plane_c_kernel<n_, false, false>), grid, block, 0, s, y1, plane, npair,  \
+                         mapct, ng, y, ldy);                                                                     \
+    break;
+    GW_FFT_SIZES(GW_CASE)
+#undef GW_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_add_adjoint(const float2 *x, int n, float2 *out, hipStream_t s) {
+  dim3 grid((n + 31) / 32, (n + 31) / 32);
+  if (grid.y > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(add_adjoint_kernel, grid, dim3(256), 0, s, x, n, out);
   return hipGetLastError();
 }
 

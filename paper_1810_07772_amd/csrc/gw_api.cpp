@@ -217,6 +217,27 @@ void build_sphere_plan(gw_grid g, const int *miller, int ng, SpherePlan &p) {
   p.bc = (int)std::min<long long>(bc, nr);
   p.a1_elems = (size_t)rowsA * p.bc;
   p.a2_elems = (size_t)g.n1 * p.npair * p.bc;
+  // row-contiguous form: the k2 values with sphere pairs, (k2, k3) -> pair slot, (k1, pair) -> sphere index
+  p.mapK2.clear(); p.mapAB.clear(); p.mapCT.clear();
+  p.plane = plane_path_supported(g.n2, g.n3);
+  p.nk2 = 0;
+  p.y1_elems = 0;
+  if (p.plane) {
+    for (int k2 = 0; k2 < g.n2; ++k2) {
+      bool any = false;
+      for (int j = 0; j < p.m3count; ++j) any = any || pair[k2 * p.m3count + j] >= 0;
+      if (any) p.mapK2.push_back(k2);
+    }
+    p.nk2 = (int)p.mapK2.size();
+    p.mapAB.assign((size_t)p.nk2 * g.n3, -1);
+    for (int sl = 0; sl < p.nk2; ++sl)
+      for (int k3 = 0; k3 < g.n3; ++k3)
+        if (idx3[k3] >= 0) p.mapAB[(size_t)sl * g.n3 + k3] = pair[p.mapK2[sl] * p.m3count + idx3[k3]];
+    p.mapCT.assign((size_t)g.n1 * p.npair, -1);
+    for (int pi = 0; pi < p.npair; ++pi)
+      for (int k1 = 0; k1 < g.n1; ++k1) p.mapCT[(size_t)k1 * p.npair + pi] = p.mapC[(size_t)pi * g.n1 + k1];
+    p.y1_elems = (size_t)nr * g.n1 * p.npair;
+  }
 }
 
 // One 3-D transform over the row index of `in` ([nr][B], row stride ld_in) to `out` ([ng][B],
@@ -235,9 +256,23 @@ hipError_t transform_rows(const SpherePlan &p, int sign, const float2 *in, long 
 }
 
 hipError_t enqueue_sphere_transform(const SpherePlan &p, const SphereBuffers &b, const float2 *p_rr, float2 *p_gg,
-                                    hipStream_t s) {
+                                    bool herm, hipStream_t s) {
   const int nr = p.n1 * p.n2 * p.n3, ng = p.ng;
   hipError_t e;
+  if (p.plane && b.y1) {
+    // rows of M (P itself, or for a Hermitian P its upper triangle with half the diagonal), contiguous:
+    // Y[r][g'] = sum_r' M(r, r') exp(+i G'.r')
+    if ((e = launch_plane_ab(p.n3, herm, p_rr, nr, nr, p.n1, b.dK2, p.nk2, b.dAB, p.npair, b.y1, s)) != hipSuccess)
+      return e;
+    if ((e = launch_plane_c(p.n1, herm, b.y1, nr, p.n2 * p.n3, p.npair, b.dCT, ng, b.ph, ng, s)) != hipSuccess)
+      return e;
+    // X(g, g') = sum_r exp(-i G.r) Y[r][g'], then P~ = X (general P) or X + X^H (P = M + M^H)
+    float2 *x = herm ? b.q : p_gg;
+    if ((e = transform_rows(p, -1, b.ph, ng, ng, x, ng, b.a1, b.a2, std::min(p.bc, ng), b.dA, b.dB, b.dC, s)) !=
+        hipSuccess)
+      return e;
+    return herm ? launch_add_adjoint(b.q, ng, p_gg, s) : hipSuccess;
+  }
   // rows: P^(g, r') = sum_r exp(-i G.r) P(r, r')
   if ((e = transform_rows(p, -1, p_rr, nr, nr, b.ph, nr, b.a1, b.a2, p.bc, b.dA, b.dB, b.dC, s)) != hipSuccess) return e;
   // columns: transpose, then Q(g', g) = sum_r' exp(+i G'.r') P^T(r', g), and p_gg = Q^T
@@ -252,7 +287,7 @@ hipError_t enqueue_sphere_transform(const SpherePlan &p, const SphereBuffers &b,
 // list and stream of the slot's previous upload reuses the device maps: no host rebuild, and no
 // pageable copy that would stall the stream.  `p` receives the plan's sizes (its host maps stay empty).
 int upload_plan(gw_ctx *ctx, gw_grid g, const int *miller, int ng, int map_slot, SpherePlan &p, int **dA, int **dB,
-                int **dC, hipStream_t s) {
+                int **dC, hipStream_t s, const int **extra) {
   std::unique_ptr<PlanCacheEntry> &e = ctx->plans[map_slot];
   const size_t nm = (size_t)ng * 3;
   const bool same = e && e->g.n1 == g.n1 && e->g.n2 == g.n2 && e->g.n3 == g.n3 && e->miller.size() == nm &&
@@ -270,21 +305,32 @@ int upload_plan(gw_ctx *ctx, gw_grid g, const int *miller, int ng, int map_slot,
   }
   const SpherePlan &pl = e->plan;
   const size_t nA = pl.mapA.size(), nB = pl.mapB.size(), nC = pl.mapC.size();
+  const size_t nK = pl.mapK2.size(), nAB = pl.mapAB.size(), nCT = pl.mapCT.size();
   void *maps;
-  GW_STATUS(ws_get(ctx, map_slot, (nA + nB + nC) * sizeof(int), &maps, s));
+  GW_STATUS(ws_get(ctx, map_slot, pl.maps_ints() * sizeof(int), &maps, s));
   *dA = (int *)maps;
   *dB = *dA + nA;
   *dC = *dB + nB;
+  int *dK = *dC + nC, *dAB = dK + nK, *dCT = dAB + nAB;
   if (!same || maps != e->maps) {
     e->maps = nullptr;   // not valid until every copy below is queued
     GW_HIP(ctx, hipMemcpyAsync(*dA, pl.mapA.data(), nA * sizeof(int), hipMemcpyHostToDevice, s));
     GW_HIP(ctx, hipMemcpyAsync(*dB, pl.mapB.data(), nB * sizeof(int), hipMemcpyHostToDevice, s));
     GW_HIP(ctx, hipMemcpyAsync(*dC, pl.mapC.data(), nC * sizeof(int), hipMemcpyHostToDevice, s));
+    if (nK) GW_HIP(ctx, hipMemcpyAsync(dK, pl.mapK2.data(), nK * sizeof(int), hipMemcpyHostToDevice, s));
+    if (nAB) GW_HIP(ctx, hipMemcpyAsync(dAB, pl.mapAB.data(), nAB * sizeof(int), hipMemcpyHostToDevice, s));
+    if (nCT) GW_HIP(ctx, hipMemcpyAsync(dCT, pl.mapCT.data(), nCT * sizeof(int), hipMemcpyHostToDevice, s));
     e->maps = maps;
+  }
+  if (extra) {
+    extra[0] = dK;
+    extra[1] = dAB;
+    extra[2] = dCT;
   }
   p.n1 = pl.n1; p.n2 = pl.n2; p.n3 = pl.n3; p.ng = pl.ng;
   p.m3count = pl.m3count; p.npair = pl.npair;
   p.bc = pl.bc; p.a1_elems = pl.a1_elems; p.a2_elems = pl.a2_elems;
+  p.plane = pl.plane; p.nk2 = pl.nk2; p.y1_elems = pl.y1_elems;
   return GW_OK;
 }
 
@@ -292,20 +338,42 @@ int upload_plan(gw_ctx *ctx, gw_grid g, const int *miller, int ng, int map_slot,
 
 namespace {
 
+// The triangle form P~ = X + X^H (X from the upper triangle of P) forms the row and column of a sphere
+// vector with |q+G| -> 0 as the difference of two large partial sums (only the whole P's column sums
+// cancel, the triangle's do not), and the Coulomb factor sqrt(V) ~ 1/|q+G| carries that rounding into
+// eps.  Builds whose sphere holds a vector with 0 < |q+m| < kTriangleMinQ (crystal units) use the
+// full-matrix form; at |q+m| = 0 the head rule removes that row from eps.
+constexpr double kTriangleMinQ = 1e-2;
+}  // namespace
+
+bool gwi::triangle_form_suits(const double *q, const int *miller, int ng) {
+  for (int i = 0; i < ng; ++i) {
+    const double x = miller[3 * i] + q[0], y = miller[3 * i + 1] + q[1], z = miller[3 * i + 2] + q[2];
+    const double d = std::sqrt(x * x + y * y + z * z);
+    if (d > 0.0 && d < kTriangleMinQ) return false;
+  }
+  return true;
+}
+
+namespace {
+
 int sphere_transform_impl(gw_ctx *ctx, const float2 *p_rr, gw_grid g, const int *miller, int ng, float2 *p_gg,
-                          hipStream_t s) {
+                          bool herm, hipStream_t s) {
   SpherePlan plan;
   int *dA, *dB, *dC;
-  GW_STATUS(upload_plan(ctx, g, miller, ng, WS_FFT_MAP, plan, &dA, &dB, &dC, s));
+  const int *extra[3] = {nullptr, nullptr, nullptr};
+  GW_STATUS(upload_plan(ctx, g, miller, ng, WS_FFT_MAP, plan, &dA, &dB, &dC, s, extra));
   const int nr = g.n1 * g.n2 * g.n3;
-  void *a1, *a2, *ph, *pht, *q;
+  void *a1, *a2, *ph, *pht = nullptr, *q, *y1 = nullptr;
   GW_STATUS(ws_get(ctx, WS_FFT_A, plan.a1_elems * sizeof(float2), &a1, s));
   GW_STATUS(ws_get(ctx, WS_FFT_B, plan.a2_elems * sizeof(float2), &a2, s));
   GW_STATUS(ws_get(ctx, WS_COUNT_BASE + 0, (size_t)ng * nr * sizeof(float2), &ph, s));
-  GW_STATUS(ws_get(ctx, WS_COUNT_BASE + 1, (size_t)ng * nr * sizeof(float2), &pht, s));
+  if (plan.plane) GW_STATUS(ws_get(ctx, WS_COUNT_BASE + 2, plan.y1_elems * sizeof(float2), &y1, s));
+  else GW_STATUS(ws_get(ctx, WS_COUNT_BASE + 1, (size_t)ng * nr * sizeof(float2), &pht, s));
   GW_STATUS(ws_get(ctx, WS_PGG_T, (size_t)ng * ng * sizeof(float2), &q, s));
-  SphereBuffers b{(float2 *)a1, (float2 *)a2, (float2 *)ph, (float2 *)pht, (float2 *)q, dA, dB, dC};
-  GW_HIP(ctx, enqueue_sphere_transform(plan, b, p_rr, p_gg, s));
+  SphereBuffers b{(float2 *)a1, (float2 *)a2, (float2 *)ph, (float2 *)pht, (float2 *)q, dA, dB, dC,
+                  (float2 *)y1, extra[0], extra[1], extra[2]};
+  GW_HIP(ctx, enqueue_sphere_transform(plan, b, p_rr, p_gg, herm, s));
   return GW_OK;
 }
 
@@ -365,7 +433,12 @@ int hpd_inverse_impl(gw_ctx *ctx, double2 *a, int n, double2 *out, hipStream_t s
   GW_STATUS(ws_get(ctx, WS_CHOL_X, (size_t)n * n * sizeof(double2), &x, s));
   GW_STATUS(ws_get(ctx, WS_CHOL_SMALL, chol_small_bytes(n) + 256, &sm, s));
   piv = (char *)sm + chol_small_bytes(n);
-  GW_HIP(ctx, hpd_inverse(a, n, (double2 *)l, (double2 *)x, (double2 *)sm, (int *)piv, out, s));
+  if (!ctx->chol_side) {
+    GW_HIP(ctx, hipStreamCreateWithFlags(&ctx->chol_side, hipStreamNonBlocking));
+    for (hipEvent_t &e : ctx->chol_ev) GW_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  GW_HIP(ctx, hpd_inverse(a, n, (double2 *)l, (double2 *)x, (double2 *)sm, (int *)piv, out, s, ctx->chol_side,
+                          ctx->chol_ev[0], ctx->chol_ev[1]));
   GW_HIP(ctx, hipMemcpyAsync(ctx->pivot_host, piv, sizeof(int), hipMemcpyDeviceToHost, s));
   GW_HIP(ctx, hipStreamSynchronize(s));
   if (*ctx->pivot_host != 0) {
@@ -444,6 +517,10 @@ int gw_destroy(gw_ctx *ctx) {
   if (ctx->device >= 0) {
     if (hipSetDevice(ctx->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) st = GW_E_HIP;
     gwi::batched_release(ctx);
+    gwi::tail_graphs_release(ctx);
+    for (hipEvent_t e : ctx->chol_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (ctx->chol_side) (void)hipStreamDestroy(ctx->chol_side);
     for (auto &sl : ctx->slots)
       if (sl.ptr) (void)hipFree(sl.ptr);
     if (ctx->pivot_host) (void)hipHostFree(ctx->pivot_host);
@@ -509,7 +586,18 @@ int gw_sphere_transform(gw_ctx *ctx, const gw_c32 *p_rr, gw_grid grid, const int
   GW_STATUS(check_sphere(ctx, grid, g_miller, ng));
   GW_STATUS(grid_supported(ctx, grid));
   if (ctx->device < 0) return GW_OK;
-  return sphere_transform_impl(ctx, (const float2 *)p_rr, grid, g_miller, ng, (float2 *)p_gg, as_stream(stream));
+  return sphere_transform_impl(ctx, (const float2 *)p_rr, grid, g_miller, ng, (float2 *)p_gg, false, as_stream(stream));
+}
+
+int gw_sphere_transform_herm(gw_ctx *ctx, const gw_c32 *p_rr, gw_grid grid, const int *g_miller, int ng,
+                             gw_c32 *p_gg, void *stream) {
+  GW_STATUS(begin(ctx));
+  GW_CHECK(ctx, p_rr && p_gg, "p_rr and p_gg must not be NULL");
+  GW_STATUS(check_grid(ctx, grid));
+  GW_STATUS(check_sphere(ctx, grid, g_miller, ng));
+  GW_STATUS(grid_supported(ctx, grid));
+  if (ctx->device < 0) return GW_OK;
+  return sphere_transform_impl(ctx, (const float2 *)p_rr, grid, g_miller, ng, (float2 *)p_gg, true, as_stream(stream));
 }
 
 int gw_orbitals_to_grid(gw_ctx *ctx, const gw_c32 *coeff, int nb, int npw, gw_grid grid, const int *pw_miller,
@@ -580,7 +668,9 @@ int gw_polarizability(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const gw_c32 *
   }
   GW_STATUS(polarizability_r_impl(ctx, (const float2 *)psi_occ, nv, (const float2 *)psi_unocc, nc, nr, e_v, e_c, o,
                                   prr, s));
-  return sphere_transform_impl(ctx, prr, grid, g_miller, ng, (float2 *)p_gg, s);
+  // the update writes a Hermitian P (with accumulate the caller's earlier contents are part of it)
+  return sphere_transform_impl(ctx, prr, grid, g_miller, ng, (float2 *)p_gg,
+                               !o.accumulate && triangle_form_suits(q, g_miller, ng), s);
 }
 
 int gw_epsilon(gw_ctx *ctx, const gw_c32 *p_gg, int ng, gw_grid grid, const double *q, const int *g_miller,

@@ -67,7 +67,7 @@ void store_tune_file(const std::string &key, int tile) {
 
 // Workspace slots private to the batched path (so a graph's baked-in addresses stay valid).
 enum {
-  BS_P0 = 64, BS_P1, BS_A1, BS_A2, BS_PH, BS_PHT, BS_Q, BS_EPS, BS_L, BS_X, BS_SMALL, BS_PIVOT,
+  BS_P0 = 64, BS_P1, BS_A1, BS_A2, BS_PH, BS_PHT, BS_Q, BS_EPS, BS_L, BS_X, BS_SMALL, BS_PIVOT, BS_Y1,
   BS_JOB_BASE = 96   // per job: 6 slots each (energies, scale, band exponents, maps, miller, sqrtv)
 };
 constexpr int kJobSlots = 6;
@@ -230,11 +230,12 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
   // ---- plans, tiles and workspace (all before any capture) ---------------------------------
   std::vector<SpherePlan> plans(nq);
   std::vector<int> tiles(nq);
-  size_t a1 = 0, a2 = 0, ngmax = 0;
+  size_t a1 = 0, a2 = 0, ngmax = 0, y1 = 0;
   for (int j = 0; j < nq; ++j) {
     build_sphere_plan(grid, jobs[j].g_miller, jobs[j].ng, plans[j]);
     a1 = std::max(a1, plans[j].a1_elems);
     a2 = std::max(a2, plans[j].a2_elems);
+    y1 = std::max(y1, plans[j].y1_elems);
     ngmax = std::max(ngmax, (size_t)jobs[j].ng);
   }
   const int np = nq > 1 ? 2 : 1;
@@ -253,18 +254,20 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
     }
     tiles[j] = t;
   }
-  void *wa1, *wa2, *wph, *wpht, *wq, *weps, *wl, *wx, *wsmall, *wpiv;
+  void *wa1, *wa2, *wph, *wpht = nullptr, *wq, *weps, *wl, *wx, *wsmall, *wpiv, *wy1 = nullptr;
   GWX_STATUS(api_ws_get(ctx, BS_A1, a1 * sizeof(float2), &wa1, s));
   GWX_STATUS(api_ws_get(ctx, BS_A2, a2 * sizeof(float2), &wa2, s));
   GWX_STATUS(api_ws_get(ctx, BS_PH, ngmax * nr * sizeof(float2), &wph, s));
-  GWX_STATUS(api_ws_get(ctx, BS_PHT, ngmax * nr * sizeof(float2), &wpht, s));
+  // the row-contiguous transform (every job shares the grid, so all or none of the plans use it)
+  if (plans[0].plane) GWX_STATUS(api_ws_get(ctx, BS_Y1, y1 * sizeof(float2), &wy1, s));
+  else GWX_STATUS(api_ws_get(ctx, BS_PHT, ngmax * nr * sizeof(float2), &wpht, s));
   GWX_STATUS(api_ws_get(ctx, BS_Q, ngmax * ngmax * sizeof(float2), &wq, s));
   GWX_STATUS(api_ws_get(ctx, BS_EPS, ngmax * ngmax * sizeof(double2), &weps, s));
   GWX_STATUS(api_ws_get(ctx, BS_L, ngmax * ngmax * sizeof(double2), &wl, s));
   GWX_STATUS(api_ws_get(ctx, BS_X, ngmax * ngmax * sizeof(double2), &wx, s));
   GWX_STATUS(api_ws_get(ctx, BS_SMALL, chol_small_bytes((int)ngmax), &wsmall, s));
   GWX_STATUS(api_ws_get(ctx, BS_PIVOT, (size_t)nq * 64, &wpiv, s));
-  for (void *p : {wa1, wa2, wph, wpht, wq, weps, wl, wx, wsmall, wpiv}) ptrs.push_back(p);
+  for (void *p : {wa1, wa2, wph, wpht, wq, weps, wl, wx, wsmall, wpiv, wy1}) ptrs.push_back(p);
   struct JobDev { double *energy; float *scale; int *bexp; int *maps; int *miller; double *sqrtv; };
   std::vector<JobDev> jd(nq);
   for (int j = 0; j < nq; ++j) {
@@ -273,7 +276,7 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
     void *p[kJobSlots];
     const size_t bytes[kJobSlots] = {(size_t)(nv + nc) * sizeof(double), (size_t)nv * scale_ld(nc) * sizeof(float),
                                      band_exp_ints(nv, nc) * sizeof(int),
-                                     (pl.mapA.size() + pl.mapB.size() + pl.mapC.size()) * sizeof(int),
+                                     pl.maps_ints() * sizeof(int),
                                      (size_t)ng * 3 * sizeof(int), (size_t)ng * sizeof(double)};
     for (int k = 0; k < kJobSlots; ++k) {
       GWX_STATUS(api_ws_get(ctx, BS_JOB_BASE + kJobSlots * j + k, bytes[k], &p[k], s));
@@ -294,6 +297,11 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
     GWX_HIP(ctx, hipMemcpyAsync(m, pl.mapB.data(), pl.mapB.size() * sizeof(int), hipMemcpyHostToDevice, s));
     m += pl.mapB.size();
     GWX_HIP(ctx, hipMemcpyAsync(m, pl.mapC.data(), pl.mapC.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    m += pl.mapC.size();
+    for (const std::vector<int> *v : {&pl.mapK2, &pl.mapAB, &pl.mapCT}) {
+      if (!v->empty()) GWX_HIP(ctx, hipMemcpyAsync(m, v->data(), v->size() * sizeof(int), hipMemcpyHostToDevice, s));
+      m += v->size();
+    }
     GWX_HIP(ctx, hipMemcpyAsync(jd[j].miller, jb.g_miller, (size_t)jb.ng * 3 * sizeof(int), hipMemcpyHostToDevice, s));
   }
 
@@ -360,11 +368,16 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
       ck(hipStreamWaitEvent(c->sb, ev_herk[j], 0));
       const SpherePlan &pl = plans[j];
       const int *dA = jd[j].maps, *dB = dA + pl.mapA.size(), *dC = dB + pl.mapB.size();
-      SphereBuffers sbuf{(float2 *)wa1, (float2 *)wa2, (float2 *)wph, (float2 *)wpht, (float2 *)wq, dA, dB, dC};
-      ck(enqueue_sphere_transform(pl, sbuf, pj, (float2 *)jb.p_gg, c->sb));
+      const int *dK = dC + pl.mapC.size(), *dAB = dK + pl.mapK2.size(), *dCT = dAB + pl.mapAB.size();
+      SphereBuffers sbuf{(float2 *)wa1, (float2 *)wa2, (float2 *)wph, (float2 *)wpht, (float2 *)wq, dA, dB, dC,
+                         (float2 *)wy1, dK, dAB, dCT};
+      ck(enqueue_sphere_transform(pl, sbuf, pj, (float2 *)jb.p_gg, triangle_form_suits(jb.q, jb.g_miller, ng), c->sb));
       if (jb.eps_inv) {
         ck(launch_sqrtv(jd[j].miller, ng, jb.q[0], jb.q[1], jb.q[2], grid.a_bohr, jd[j].sqrtv, c->sb));
         ck(launch_eps_build((const float2 *)jb.p_gg, ng, jd[j].sqrtv, head, (double2 *)weps, c->sb));
+        // no look-ahead inside the captured graph: the 32^3 eight-q batch with per-panel fork/join events
+        // ended the process during capture, with no cause found in this code; the graph already overlaps
+        // this factorisation with the next job's update
         ck(hpd_inverse((double2 *)weps, ng, (double2 *)wl, (double2 *)wx, (double2 *)wsmall,
                        (int *)((char *)wpiv + 64 * j), (double2 *)jb.eps_inv, c->sb));
       }

@@ -26,6 +26,9 @@ struct gw_ctx {
   std::vector<Slot> slots;    // grow-only named workspace buffers
   int *pivot_host = nullptr;  // pinned host word for the Cholesky pivot flag
   void *graph_cache = nullptr;  // batched-q graphs (owned; see gw_batched.cpp)
+  void *tail_graphs = nullptr;  // training-step graphs of the learned tail (owned; see gw_tail.cpp)
+  hipStream_t chol_side = nullptr;           // second stream of the Cholesky look-ahead (default priority)
+  hipEvent_t chol_ev[2] = {nullptr, nullptr};
   std::map<std::string, int> tuned;   // autotuned update tiles, keyed by arch and shape
   bool tune_loaded = false;           // the autotune cache file has been read
   std::string arch;                   // device architecture name (cached)
@@ -107,8 +110,12 @@ hipError_t launch_eps_build(const float2 *p_gg, int ng, const double *sv, double
 // Cholesky-based inverse of a Hermitian PD matrix (lower triangle of a read).  a is overwritten.
 // l, x: n*n workspaces; small: workspace of at least chol_small_bytes(n); pivot_dev: device int.
 size_t chol_small_bytes(int n);
+// side, ev_fork, ev_side (all or none): a second stream and two events for the look-ahead, which moves
+// each panel's large trailing product off the chain of the next panel; the call returns with `side`
+// joined into `s`.
 hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small, int *pivot_dev, double2 *out,
-                       hipStream_t s);
+                       hipStream_t s, hipStream_t side = nullptr, hipEvent_t ev_fork = nullptr,
+                       hipEvent_t ev_side = nullptr);
 hipError_t launch_fill_int(int *p, int value, hipStream_t s);
 // C = alpha op(A) op(B) + beta C, complex128, op = identity (0) or conjugate transpose (1); row-major.
 hipError_t launch_zgemm(int M, int N, int K, const double2 *A, long long lda, int transA, const double2 *B,
@@ -162,8 +169,13 @@ hipError_t tail_features(const float2 *p, int ng, const int *miller, const doubl
                          double e_max, float *feat, hipStream_t s);
 hipError_t tail_target(const float2 *full, const float2 *trunc, int ng, float2 *t, hipStream_t s);
 hipError_t tail_forward(const gw_mlp &w, const float *feat, int n, float *ws, float *out, hipStream_t s);
-hipError_t tail_train_step(gw_mlp &w, gw_adam &a, const float *feat, const float2 *target, int n, float *ws,
-                           float *loss_out, hipStream_t s);
+hipError_t tail_train_step(const gw_mlp &w, const gw_adam &a, const float *feat, const float2 *target, int n,
+                           float *ws, float *loss_out, int *step_dev, int set_step, hipStream_t s);
+void tail_graphs_release(gw_ctx *ctx);
+hipError_t tail_residual_parts(const gw_mlp &w, const float *feat, const float2 *target, int n, float *ws,
+                               float *parts, hipStream_t s);
+hipError_t tail_fit_norm(int nsys, const float *const *feats, const int *ngs, double *acc, float *norm,
+                         hipStream_t s);
 hipError_t tail_sync_weights(gw_mlp &w, const float *master, hipStream_t s);
 hipError_t tail_loss(const gw_mlp &w, const float *feat, const float2 *target, int n, float *ws, float *loss_out,
                      hipStream_t s);
@@ -181,6 +193,14 @@ struct SpherePlan {
   std::vector<int> mapA, mapB, mapC;
   int bc = 0;                      // column chunk of the row passes
   size_t a1_elems = 0, a2_elems = 0;
+  // row-contiguous form (plane_ab_kernel / plane_c_kernel; only when n2 == n3, see plane_path_supported)
+  bool plane = false;
+  int nk2 = 0;                     // k2 values that occur in a sphere pair
+  std::vector<int> mapK2;          // [nk2] those k2 (grid indices 0 .. n2-1)
+  std::vector<int> mapAB;          // [nk2][n3] pair slot of (k2, k3) or -1
+  std::vector<int> mapCT;          // [n1][npair] sphere index of (k1, pair) or -1
+  size_t y1_elems = 0;             // [nr][n1][npair] intermediate
+  size_t maps_ints() const { return mapA.size() + mapB.size() + mapC.size() + mapK2.size() + mapAB.size() + mapCT.size(); }
 };
 void build_sphere_plan(gw_grid g, const int *miller, int ng, SpherePlan &p);
 struct PlanCacheEntry {
@@ -193,18 +213,33 @@ struct PlanCacheEntry {
 struct SphereBuffers {
   float2 *a1, *a2, *ph, *pht, *q;  // pass intermediates, P^ [ng][nr], its transpose, Q [ng][ng]
   const int *dA, *dB, *dC;         // device copies of the plan's maps
+  float2 *y1 = nullptr;            // row-contiguous form: [nr][n1][npair] (plan.y1_elems)
+  const int *dK2 = nullptr, *dAB = nullptr, *dCT = nullptr;
 };
+// P~ from P(r,r') [nr][nr].  herm: P is Hermitian (as the update writes it), so only its upper
+// triangle is read.  The row-contiguous form runs where the plan allows it (b.y1 set), else the
+// strided passes.
 hipError_t enqueue_sphere_transform(const SpherePlan &p, const SphereBuffers &b, const float2 *p_rr, float2 *p_gg,
-                                    hipStream_t s);
+                                    bool herm, hipStream_t s);
+bool plane_path_supported(int n2, int n3);
+// Whether the triangle (Hermitian) form of the transforms suits a build at q with this sphere: no vector
+// with 0 < |q+m| < 1e-2 (crystal units), whose Coulomb factor would amplify that form's head-row rounding.
+bool triangle_form_suits(const double *q, const int *miller, int ng);
+hipError_t launch_plane_ab(int n, bool herm, const float2 *p, long long ldp, int nr, int n1, const int *k2list, int nk2,
+                           const int *mapab, int npair, float2 *y1, hipStream_t s);
+hipError_t launch_plane_c(int n1, bool herm, const float2 *y1, int nr, int plane, int npair, const int *mapct, int ng,
+                          float2 *y, long long ldy, hipStream_t s);
+hipError_t launch_add_adjoint(const float2 *x, int n, float2 *out, hipStream_t s);
 // One 3-D transform over the row index of `in` ([nr][B], row stride ld_in) to the sphere rows of
 // `out` ([ng][B], row stride ld_out), in column chunks of at most bc (a1, a2 hold rowsA*bc and
 // n1*npair*bc elements).
 hipError_t transform_rows(const SpherePlan &p, int sign, const float2 *in, long long ld_in, int B, float2 *out,
                           long long ld_out, float2 *a1, float2 *a2, int bc, const int *dA, const int *dB,
                           const int *dC, hipStream_t s);
-// Build the sphere plan and copy its maps into workspace slot `map_slot`.
+// Build the sphere plan and copy its maps into workspace slot `map_slot` (all six maps, in the order
+// A, B, C, K2, AB, CT; `extra`, if given, receives the device addresses of K2, AB and CT).
 int upload_plan(gw_ctx *ctx, gw_grid g, const int *miller, int ng, int map_slot, SpherePlan &p, int **dA, int **dB,
-                int **dC, hipStream_t s);
+                int **dC, hipStream_t s, const int **extra = nullptr);
 
 // ---- shared host helpers of gw_api.cpp used by the batched path ---------------------------------
 int api_ws_get(gw_ctx *ctx, int slot, size_t bytes, void **out, hipStream_t s);

@@ -704,6 +704,245 @@ __global__ __launch_bounds__((1 + NPW) * NTHR, 1) void herk_split_ws_kernel(cons
 }
 
 // ---------------------------------------------------------------------------------------------
+// Wide wave-specialised split kernel: a 128 x 256 output block per workgroup (one 128-row block I and
+// the two 128-column blocks 2 jp, 2 jp + 1), twelve waves.  Waves 0-7 issue the MFMAs, two per SIMD,
+// each on a 64 x 64 quadrant (row half w >> 2, column quarter w & 3); waves 8-11, one per SIMD, form
+// and split the pair products of the block's 384 points (128 rows, 256 columns) for the next stage of
+// WK = 16 pairs.  Per stage the producers form 384 x 16 pair products for 384 MFMAs, 3 VALU instructions
+// per MFMA against 4 for the 128 x 128 block, where the 256 points' 32 pairs feed as many MFMAs.
+// Producer work: unit u = lane + 256 j (j < 3) of the 768 (point, half of the stage's pairs) units;
+// point u % 384, pairs 8 (u / 384) .. +7, so each lane keeps 3 x 8 psi_c values for the nv stages of an
+// unoccupied chunk, and the half (hence the scale row) is uniform across each wave.
+// A block whose second column block lies above the diagonal (I even, jp = I / 2) leaves it unused.
+// ---------------------------------------------------------------------------------------------
+constexpr int WK = 16;                 // pairs per stage
+constexpr int WPTS = 3 * HB;           // points of a block: 128 rows + 256 columns
+
+// block t of the row-major enumeration of (I, jp) with 0 <= jp <= I / 2: row I holds I / 2 + 1 blocks,
+// so the rows before I = 2m hold m (m + 1) blocks and those before I = 2m + 1 hold (m + 1)^2
+__device__ __forceinline__ void wide_block_of(int t, int &bi, int &jp) {
+  int m = (int)sqrtf((float)t);                 // candidate: rows before 2m + 1 hold (m + 1)^2 > t
+  while ((m + 1) * (m + 1) <= t) ++m;
+  while (m > 0 && m * m > t) --m;
+  // now m^2 <= t < (m + 1)^2: I is 2m - 1 (if t < m (m + 1)... measured from the row starts below)
+  const int start_even = m * (m + 1), start_odd = (m + 1) * (m + 1);   // first blocks of rows 2m, 2m + 1
+  if (t >= start_odd) { bi = 2 * m + 1; jp = t - start_odd; }
+  else if (t >= start_even) { bi = 2 * m; jp = t - start_even; }
+  else { bi = 2 * m - 1; jp = t - m * m; }        // row 2m - 1 starts at m^2
+}
+
+int wide_block_count(int nb) {                   // blocks over row blocks 0 .. nb-1
+  const int m = nb / 2;
+  return (nb & 1) ? (m + 1) * (m + 1) : m * (m + 1);
+}
+
+template <typename T, bool SCALED>
+__global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_kernel(const float2 *__restrict__ psi_v,
+                                                                      const float2 *__restrict__ psi_c,
+                                                                      const float *__restrict__ scale, int ldsc,
+                                                                      const int *__restrict__ band_exp,
+                                                                      float2 *__restrict__ P, int nr, int nv, int nc,
+                                                                      int nblocks, int accumulate) {
+  typedef typename SplitTraits<T>::vec vec;
+  constexpr int SRW = 2 * WK + 8;   // narrow elements per point row (padded against bank conflicts)
+  __shared__ __attribute__((aligned(16))) T sH[2][WPTS][SRW];
+  __shared__ __attribute__((aligned(16))) T sL[2][WPTS][SRW];
+  const int *order = SCALED ? band_exp + nv : nullptr, *esorted = SCALED ? band_exp + 2 * nv : nullptr;
+
+  int bi, jp;
+  wide_block_of(xcd_remap(blockIdx.x, nblocks), bi, jp);
+  const int I0 = bi * HB, J0 = 2 * jp * HB;
+  const int ncb = (2 * jp + 1 <= bi) ? 2 : 1;          // column blocks of the pair on or below the diagonal
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nchc = (nc + WK - 1) / WK;
+  const int nch = nv * nchc;
+
+  if (wave >= 8) {
+    // ---- producers
+    const int pw = wave - 8;
+    int gpt[3], half[3], row[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int u = lane + 64 * pw + 256 * j;
+      const int pt = u % WPTS;
+      // 64 pw + 256 j never straddles a multiple of 384 within a wave, so the half is wave-uniform
+      half[j] = __builtin_amdgcn_readfirstlane((64 * pw + 256 * j) / WPTS);
+      row[j] = pt;
+      // points past nr only feed outputs that are never stored: clamp the address
+      gpt[j] = min(pt < HB ? I0 + pt : J0 + (pt - HB), nr - 1);
+    }
+    float2 pc[3][8], pcn[3][8], pvv[3];
+    float sc[2][8];
+    auto load_c = [&](float2 (&dst)[3][8], int cc) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          dst[j][k] = psi_c[(size_t)min(cc * WK + 8 * half[j] + k, nc - 1) * nr + gpt[j]];
+    };
+    auto load_v = [&](int ch) {
+      const int vi = ch % nv, c0 = (ch / nv) * WK;
+      const int v = SCALED ? order[vi] : vi;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) pvv[j] = psi_v[(size_t)v * nr + gpt[j]];
+      if (SCALED) {
+        const float m = ldexpf(1.0f, esorted[vi]);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) { pvv[j].x *= m; pvv[j].y *= m; }
+      }
+      const float *srow = scale + (size_t)v * ldsc + c0;     // zero past nc: those pair products vanish
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sc[h][k] = srow[8 * h + k];
+    };
+    auto produce = [&](int buf) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        u32x4 *dh = reinterpret_cast<u32x4 *>(&sH[buf][row[j]][16 * half[j]]);
+        u32x4 *dl = reinterpret_cast<u32x4 *>(&sL[buf][row[j]][16 * half[j]]);
+        const float *s8 = half[j] ? sc[1] : sc[0];
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+          u32x4 hv, lv;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int k = 4 * g + m;
+            const float fx = (pvv[j].x * pc[j][k].x + pvv[j].y * pc[j][k].y) * s8[k];
+            const float fy = (pvv[j].x * pc[j][k].y - pvv[j].y * pc[j][k].x) * s8[k];
+            unsigned w, wl;
+            NarrowSplit<T>::split(fx, fy, w, wl);
+            hv[m] = w;
+            lv[m] = wl;
+          }
+          dh[g] = hv;
+          dl[g] = lv;
+        }
+      }
+    };
+    load_c(pc, 0);
+    load_v(0);
+    produce(0);
+    if (nch > 1) load_v(1);
+    if (nv == 1 && nch > 1) load_c(pcn, 1);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+      if (ch + 1 < nch) {
+        if ((ch + 1) % nv == 0) {                          // stage ch+1 opens the next unoccupied chunk
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) pc[j][k] = pcn[j][k];
+        }
+        produce((ch & 1) ^ 1);
+        if (ch + 2 < nch) {
+          load_v(ch + 2);
+          if ((ch + 2) % nv == 0) load_c(pcn, (ch + 2) / nv);
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+
+  // ---- consumers: quadrant rows I0 + 64 wr, columns J0 + 64 wc
+  const int wr = wave >> 2, wc = wave & 3;
+  const bool active = (wc >> 1) < ncb;                     // wave-uniform: this quadrant is on or below the diagonal
+  const int kq = lane >> 5, idx = lane & 31;
+  const int ar0 = wr * 64 + idx, bc0 = HB + wc * 64 + idx;  // LDS rows of the A and B operands
+  f32x16 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) { accR[a][b][e] = 0.f; accI[a][b][e] = 0.f; }
+  auto unscale = [&](int e) {
+    const float f = ldexpf(1.0f, -2 * e);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        accR[a][b] *= f;
+        accI[a][b] *= f;
+      }
+  };
+  constexpr int FOLD_STAGES = FOLD_PAIRS / WK;
+  const int mrow = bi, mcol = 2 * jp + (wc >> 1);          // 128-blocks of this quadrant
+  const bool mirror_q = mcol != mrow;
+  int nfold = 0;
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (active) {
+      if (SCALED && ch > 0 && (ch % FOLD_STAGES) != 0) {
+        const int vi = ch % nv;
+        const int d = esorted[vi] - esorted[vi == 0 ? nv - 1 : vi - 1];
+        if (d != 0) {
+          const float f = ldexpf(1.0f, 2 * d);
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              accR[a][b] *= f;
+              accI[a][b] *= f;
+            }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < WK / 8; ++g) {
+        const int ko = g * 16 + kq * 8;
+#define GW_PROD4(ACC, A0, A1, B0, B1)                        \
+  ACC[0][0] = SplitTraits<T>::mfma(A0, B0, ACC[0][0]);        \
+  ACC[0][1] = SplitTraits<T>::mfma(A0, B1, ACC[0][1]);        \
+  ACC[1][0] = SplitTraits<T>::mfma(A1, B0, ACC[1][0]);        \
+  ACC[1][1] = SplitTraits<T>::mfma(A1, B1, ACC[1][1]);
+        const vec ah0 = *reinterpret_cast<const vec *>(&sH[buf][ar0][ko]);
+        const vec ah1 = *reinterpret_cast<const vec *>(&sH[buf][ar0 + 32][ko]);
+        vec b0 = *reinterpret_cast<const vec *>(&sH[buf][bc0][ko]);
+        vec b1 = *reinterpret_cast<const vec *>(&sH[buf][bc0 + 32][ko]);
+        GW_PROD4(accR, ah0, ah1, b0, b1)           // hi * hi
+        {
+          const vec al0 = *reinterpret_cast<const vec *>(&sL[buf][ar0][ko]);
+          const vec al1 = *reinterpret_cast<const vec *>(&sL[buf][ar0 + 32][ko]);
+          GW_PROD4(accR, al0, al1, b0, b1)         // lo * hi
+          b0 = rot_neg(b0);
+          b1 = rot_neg(b1);
+          GW_PROD4(accI, ah0, ah1, b0, b1)
+          GW_PROD4(accI, al0, al1, b0, b1)
+        }
+        b0 = *reinterpret_cast<const vec *>(&sL[buf][bc0][ko]);
+        b1 = *reinterpret_cast<const vec *>(&sL[buf][bc0 + 32][ko]);
+        GW_PROD4(accR, ah0, ah1, b0, b1)           // hi * lo
+        b0 = rot_neg(b0);
+        b1 = rot_neg(b1);
+        GW_PROD4(accI, ah0, ah1, b0, b1)
+#undef GW_PROD4
+      }
+      if ((ch + 1) % FOLD_STAGES == 0 && ch + 1 < nch) {
+        if (SCALED) unscale(esorted[ch % nv]);
+        int lane_f = lane;
+        asm volatile("" : "+v"(lane_f));
+        store_tile(P, nr, I0, J0, accumulate && mirror_q, accumulate || nfold > 0, accR, accI, wr, wc, lane_f);
+        ++nfold;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) { accR[a][b][e] = 0.f; accI[a][b][e] = 0.f; }
+      }
+    }
+    __syncthreads();
+  }
+  if (!active) return;
+  if (SCALED) unscale(esorted[(nch - 1) % nv]);
+  if (nfold == 0 || accumulate) store_tile(P, nr, I0, J0, mirror_q, accumulate || nfold > 0, accR, accI, wr, wc, lane);
+  else store_tile_after_folds(P, nr, I0, J0, mirror_q, accR, accI, wr, wc, lane);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Per-band exponents of the FP16 path: e_v = floor(log2(2^14 / bound_v)) with
 // bound_v = max_r |psi_v(r)| * max_{c,r} |psi_c(r)| * max_c s_vc >= max |f_vc(r)|, so the
 // scaled f of band v stays below 2^14 (FP16 max 65504) and its lo part stays normal for
@@ -836,6 +1075,8 @@ static const TileCfg kTiles[] = {
   {"fp16split_t128_ws_k32_scaled", GW_SPLIT_FP16_SCALED},
   {"bf16split_t128_ws2_k32", GW_SPLIT_BF16},
   {"fp16split_t128_ws2_k32_scaled", GW_SPLIT_FP16_SCALED},
+  {"bf16split_t128x256_wide_k16", GW_SPLIT_BF16},
+  {"fp16split_t128x256_wide_k16_scaled", GW_SPLIT_FP16_SCALED},
 };
 
 int herk_tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -888,6 +1129,18 @@ hipError_t launch_herk(int precision, int tile, const float2 *psi_v, const float
       GW_WS(_Float16, 32, false, true, 2);
       break;
 #undef GW_WS
+    case 13:
+    case 14: {
+      const int nw = wide_block_count(nb);
+      if (tile == 14 && !band_exp) return hipErrorInvalidValue;
+      if (tile == 13)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_wide_kernel<__bf16, false>), dim3(nw), dim3(3 * NTHR), 0, s,
+                           psi_v, psi_c, scale, ldsc, band_exp, p, nr, nv, nc, nw, accumulate);
+      else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_wide_kernel<_Float16, true>), dim3(nw), dim3(3 * NTHR), 0, s,
+                           psi_v, psi_c, scale, ldsc, band_exp, p, nr, nv, nc, nw, accumulate);
+      break;
+    }
     default:
       return hipErrorInvalidValue;
   }

@@ -3,7 +3,8 @@
 // The paper lists the truncation of the unoccupied-band sum of Eq.(Pstatic) as its first
 // technical issue.  This correction predicts, per G, the missing part of P~ from a truncated
 // build:  dP~ = -(diag(d) + U U^H) with d_G = softplus(o_G0) s_G and
-// u_Gk = (o_G,1+k + i o_G,17+k) sqrt(s_G), s_G = |Re P~_Nc(G,G)|, where o_G is a 4-128-128-33
+// u_Gk = (o_G,1+k + i o_G,17+k) sqrt(s_G) for k < r (zero beyond; the rank r <= 16 is a model setting),
+// s_G = |Re P~_Nc(G,G)|, where o_G is a 4-128-128-33
 // MLP (SiLU, BF16 weights, FP32 arithmetic) of the raw features
 // x_G = (|q+G|, log|Re P~_Nc(G,G)|, Nc/N_g, E_max) normalised by stored mean and std.
 // Training minimises ||dP~ - T||_F^2 / ||T||_F^2 with T = H(P~_4Nc) - H(P~_Nc), H(X) = (X+X^H)/2.
@@ -103,14 +104,15 @@ __global__ void tail_dense_kernel(const float *__restrict__ h, int n, int m, con
 }
 
 // ---- head, T U, U^H U, loss terms and d loss / d o ----------------------------------------------
-__global__ void tail_head_kernel(const float *__restrict__ o, const float *__restrict__ feat, int n,
+__global__ void tail_head_kernel(const float *__restrict__ o, const float *__restrict__ feat, int n, int rank,
                                  float *__restrict__ d, float2 *__restrict__ u) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const float s = expf(feat[4 * g + 1]);
   const float rs = sqrtf(s);
   d[g] = softplus(o[g * TO]) * s;
-  for (int k = 0; k < TR; ++k) u[g * TR + k] = make_float2(o[g * TO + 1 + k] * rs, o[g * TO + 1 + TR + k] * rs);
+  for (int k = 0; k < TR; ++k)
+    u[g * TR + k] = k < rank ? make_float2(o[g * TO + 1 + k] * rs, o[g * TO + 1 + TR + k] * rs) : make_float2(0.f, 0.f);
 }
 
 // W = T U, one workgroup per row g; also the row's contribution to ||T||^2.
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(256) void tail_gram_kernel(const float2 *__restrict
 __global__ void tail_grad_o_kernel(const float *__restrict__ o, const float *__restrict__ feat,
                                    const float *__restrict__ d, const float2 *__restrict__ u,
                                    const float2 *__restrict__ w, const float2 *__restrict__ gm,
-                                   const float2 *__restrict__ t, int n, const float *__restrict__ tn,
+                                   const float2 *__restrict__ t, int n, int rank, const float *__restrict__ tn,
                                    float *__restrict__ go, float *__restrict__ lrow) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
@@ -183,8 +185,8 @@ __global__ void tail_grad_o_kernel(const float *__restrict__ o, const float *__r
       bu.x += a.x * c.x - a.y * c.y;
       bu.y += a.x * c.y + a.y * c.x;
     }
-    go[g * TO + 1 + k] = 4.0f * bu.x * rs * inv;
-    go[g * TO + 1 + TR + k] = 4.0f * bu.y * rs * inv;
+    go[g * TO + 1 + k] = k < rank ? 4.0f * bu.x * rs * inv : 0.f;        // unused columns: no gradient
+    go[g * TO + 1 + TR + k] = k < rank ? 4.0f * bu.y * rs * inv : 0.f;
   }
   lrow[g] = dg * dg + 2.0f * dg * tgg + 2.0f * dg * u2 + 2.0f * uw;
 }
@@ -240,13 +242,18 @@ __global__ void tail_back_kernel(const float *__restrict__ b, int m, const __bf1
 
 // ---- Adam on the FP32 master copy, then the BF16 weights / FP32 biases of the next forward ------
 // master layout: W1 [4][128], b1 [128], W2 [128][128], b2 [128], W3 [128][33], b3 [33]
+// The step count t comes from device memory (step_dev), so the same launch replays correctly from a graph;
+// the bias corrections are 1 - beta^t.
 __global__ void tail_adam_kernel(float *__restrict__ master, float *__restrict__ m, float *__restrict__ v,
                                  const float *__restrict__ grad, int np, float lr, float b1, float b2, float eps,
-                                 float c1, float c2, __bf16 *__restrict__ wout, float *__restrict__ bout, int update) {
+                                 const int *__restrict__ step_dev, __bf16 *__restrict__ wout, float *__restrict__ bout,
+                                 int update) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= np) return;
   float p = master[i];
   if (update) {
+    const float t = (float)step_dev[0];
+    const float c1 = 1.0f - powf(b1, t), c2 = 1.0f - powf(b2, t);
     const float gi = grad[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
@@ -294,6 +301,121 @@ __global__ void tail_apply_kernel(const float2 *__restrict__ p, const float *__r
   out[idx] = make_float2(x.x - acc.x, x.y - acc.y);
 }
 
+// One more Adam step: the device step counter advances by one (first node of a captured training step).
+__global__ void tail_step_inc_kernel(int *__restrict__ step_dev) { step_dev[0] += 1; }
+
+// Residual parts of one row g of dP~ - T with dP~ = -(diag(d) + U U^H): one workgroup per row; part[g][0..3] =
+// off-diagonal |residual|^2, off-diagonal |T|^2, diagonal |residual|^2, diagonal |T|^2.
+__global__ __launch_bounds__(256) void tail_parts_kernel(const float *__restrict__ d, const float2 *__restrict__ u,
+                                                         const float2 *__restrict__ t, int n,
+                                                         float *__restrict__ part) {
+  const int g = blockIdx.x;
+  __shared__ float2 ug[TR];
+  __shared__ float red[4][256];
+  if (threadIdx.x < TR) ug[threadIdx.x] = u[g * TR + threadIdx.x];
+  __syncthreads();
+  float a[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int gp = threadIdx.x; gp < n; gp += 256) {
+    float2 c = make_float2(gp == g ? d[g] : 0.f, 0.f);
+    for (int k = 0; k < TR; ++k) {
+      const float2 x = ug[k], y = u[gp * TR + k];          // x conj(y)
+      c.x += x.x * y.x + x.y * y.y;
+      c.y += x.y * y.x - x.x * y.y;
+    }
+    const float2 tv = t[(size_t)g * n + gp];
+    const float rx = -c.x - tv.x, ry = -c.y - tv.y;
+    const int b = gp == g ? 2 : 0;
+    a[b] += rx * rx + ry * ry;
+    a[b + 1] += tv.x * tv.x + tv.y * tv.y;
+  }
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[4 * g + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Column sums of part [n][4] into out[4] (one workgroup, double accumulation).
+__global__ __launch_bounds__(256) void tail_parts_sum_kernel(const float *__restrict__ part, int n,
+                                                             float *__restrict__ out) {
+  __shared__ double red[4][256];
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int g = threadIdx.x; g < n; g += 256)
+    for (int k = 0; k < 4; ++k) a[k] += part[4 * g + k];
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[threadIdx.x] = (float)red[threadIdx.x][0];
+}
+
+// Feature statistics over a training set, one system per launch (one workgroup), merged into acc
+// (double [16]): pass 0 adds the sums (acc[0..4)) and folds min / max (acc[8..12), acc[12..16)); pass 1
+// adds the squared deviations from mean = acc[0..4) / total (acc[4..8)).  The first launch of a pass
+// initialises its entries.
+__global__ __launch_bounds__(256) void tail_stats_kernel(const float *__restrict__ feat, int n, int pass, int first,
+                                                         double total, double *__restrict__ acc) {
+  __shared__ double red[12][256];
+  double a[12];
+  for (int k = 0; k < 4; ++k) {
+    a[k] = 0.0;
+    a[4 + k] = INFINITY;
+    a[8 + k] = -INFINITY;
+  }
+  for (int g = threadIdx.x; g < n; g += 256)
+    for (int k = 0; k < 4; ++k) {
+      const double x = feat[4 * g + k];
+      if (pass == 0) {
+        a[k] += x;
+        a[4 + k] = fmin(a[4 + k], x);
+        a[8 + k] = fmax(a[8 + k], x);
+      } else {
+        const double dx = x - acc[k] / total;
+        a[k] += dx * dx;
+      }
+    }
+  for (int k = 0; k < 12; ++k) red[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int k = 0; k < 4; ++k) {
+        red[k][threadIdx.x] += red[k][threadIdx.x + st];
+        red[4 + k][threadIdx.x] = fmin(red[4 + k][threadIdx.x], red[4 + k][threadIdx.x + st]);
+        red[8 + k][threadIdx.x] = fmax(red[8 + k][threadIdx.x], red[8 + k][threadIdx.x + st]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) {
+    const int k = threadIdx.x;
+    if (pass == 0) {
+      acc[k] = (first ? 0.0 : acc[k]) + red[k][0];
+      acc[8 + k] = first ? red[4 + k][0] : fmin(acc[8 + k], red[4 + k][0]);
+      acc[12 + k] = first ? red[8 + k][0] : fmax(acc[12 + k], red[8 + k][0]);
+    } else {
+      acc[4 + k] = (first ? 0.0 : acc[4 + k]) + red[k][0];
+    }
+  }
+}
+
+// norm = mean[4], std[4] (1 where std <= 1e-12 max(1, |mean|)), min[4], max[4] as floats.
+__global__ void tail_stats_final_kernel(const double *__restrict__ acc, double total, float *__restrict__ norm) {
+  const int k = threadIdx.x;
+  if (k >= 4) return;
+  const double mean = acc[k] / total;
+  double sd = sqrt(acc[4 + k] / total);
+  if (sd <= 1e-12 * fmax(1.0, fabs(mean))) sd = 1.0;
+  norm[k] = (float)mean;
+  norm[4 + k] = (float)sd;
+  norm[8 + k] = (float)acc[8 + k];
+  norm[12 + k] = (float)acc[12 + k];
+}
+
 // ---- launch sequences ------------------------------------------------------------------------------
 #define T_LAUNCH(kernel, total, ...)                                                                      \
   do {                                                                                                    \
@@ -305,11 +427,11 @@ __global__ void tail_apply_kernel(const float2 *__restrict__ p, const float *__r
 size_t tail_ws_floats(int n) {
   // xn 4n, z1 h1 z2 h2 4*128n, o go 2*33n, d n, u w 2*(32n), trow lrow 2n, gram 512, scalars 16,
   // dz1 dz2 2*128n
-  return (size_t)n * (4 + 6 * TW + 2 * TO + 1 + 4 * TR + 2) + 2 * TR * TR + 16 + 64;
+  return (size_t)n * (4 + 6 * TW + 2 * TO + 1 + 4 * TR + 2 + 4) + 2 * TR * TR + 16 + 64;
 }
 
 struct TailWs {
-  float *xn, *z1, *h1, *z2, *h2, *o, *go, *d, *trow, *lrow, *dz1, *dz2, *sc;
+  float *xn, *z1, *h1, *z2, *h2, *o, *go, *d, *trow, *lrow, *dz1, *dz2, *part, *sc;
   float2 *u, *w, *gm;
 };
 
@@ -328,6 +450,7 @@ static TailWs carve(float *base, int n) {
   t.d = p; p += n;
   t.trow = p; p += n;
   t.lrow = p; p += n;
+  t.part = p; p += 4 * (size_t)n;
   p = (float *)(((uintptr_t)p + 15) & ~(uintptr_t)15);
   t.u = (float2 *)p; p += 2 * (size_t)TR * n;
   t.w = (float2 *)p; p += 2 * (size_t)TR * n;
@@ -367,7 +490,7 @@ static hipError_t loss_and_grad_o(const gw_mlp &w, const float *feat, const floa
   hipError_t e = forward(w, feat, n, t, t.o, s);
   if (e != hipSuccess) return e;
   // loss and d loss / d o
-  T_LAUNCH(tail_head_kernel, n, t.o, feat, n, t.d, t.u);
+  T_LAUNCH(tail_head_kernel, n, t.o, feat, n, w.rank, t.d, t.u);
   hipLaunchKernelGGL(tail_tu_kernel, dim3(n), dim3(256), 0, s, target, t.u, n, t.w, t.trow);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(tail_gram_kernel, dim3(1), dim3(256), 0, s, t.u, n, t.gm);
@@ -376,7 +499,7 @@ static hipError_t loss_and_grad_o(const gw_mlp &w, const float *feat, const floa
   hipLaunchKernelGGL(tail_reduce_kernel, dim3(1), dim3(256), 0, s, t.trow, n, tn, (const float2 *)nullptr,
                      (const float *)nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  T_LAUNCH(tail_grad_o_kernel, n, t.o, feat, t.d, t.u, t.w, t.gm, target, n, tn, t.go, t.lrow);
+  T_LAUNCH(tail_grad_o_kernel, n, t.o, feat, t.d, t.u, t.w, t.gm, target, n, w.rank, tn, t.go, t.lrow);
   hipLaunchKernelGGL(tail_reduce_kernel, dim3(1), dim3(256), 0, s, t.lrow, n, loss_out, t.gm, tn);
   return hipGetLastError();
 }
@@ -386,10 +509,18 @@ hipError_t tail_loss(const gw_mlp &w, const float *feat, const float2 *target, i
   return loss_and_grad_o(w, feat, target, n, carve(ws, n), loss_out, s);
 }
 
-hipError_t tail_train_step(gw_mlp &w, gw_adam &a, const float *feat, const float2 *target, int n, float *ws,
-                           float *loss_out, hipStream_t s) {
+// One training step.  The Adam step count lives in step_dev: with set_step >= 0 it is first written (eager
+// calls), with set_step < 0 a kernel advances it by one (the form a captured graph replays).
+hipError_t tail_train_step(const gw_mlp &w, const gw_adam &a, const float *feat, const float2 *target, int n,
+                           float *ws, float *loss_out, int *step_dev, int set_step, hipStream_t s) {
   const TailWs t = carve(ws, n);
-  hipError_t e = loss_and_grad_o(w, feat, target, n, t, loss_out, s);
+  hipError_t e = set_step >= 0 ? launch_fill_int(step_dev, set_step, s) : hipSuccess;
+  if (e != hipSuccess) return e;
+  if (set_step < 0) {
+    hipLaunchKernelGGL(tail_step_inc_kernel, dim3(1), dim3(1), 0, s, step_dev);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  e = loss_and_grad_o(w, feat, target, n, t, loss_out, s);
   if (e != hipSuccess) return e;
   // backward into a.grad (flat master layout)
   const __bf16 *w2 = (const __bf16 *)w.w + 4 * TW, *w3 = w2 + TW * TW;
@@ -403,16 +534,14 @@ hipError_t tail_train_step(gw_mlp &w, gw_adam &a, const float *feat, const float
   T_LAUNCH(tail_wgrad_kernel, 4 * TW, t.xn, 4, t.dz1, TW, n, gw1);
   T_LAUNCH(tail_bgrad_kernel, TW, t.dz1, TW, n, gb1);
   // Adam
-  a.step += 1;
-  const float c1 = 1.0f - powf(a.beta1, (float)a.step), c2 = 1.0f - powf(a.beta2, (float)a.step);
   T_LAUNCH(tail_adam_kernel, GW_TAIL_NPARAM, a.master, a.m, a.v, a.grad, GW_TAIL_NPARAM, a.lr, a.beta1, a.beta2, a.eps,
-           c1, c2, (__bf16 *)w.w, w.b, 1);
+           (const int *)step_dev, (__bf16 *)w.w, w.b, 1);
   return hipSuccess;
 }
 
 hipError_t tail_sync_weights(gw_mlp &w, const float *master, hipStream_t s) {
   T_LAUNCH(tail_adam_kernel, GW_TAIL_NPARAM, (float *)master, (float *)nullptr, (float *)nullptr, (const float *)nullptr,
-           GW_TAIL_NPARAM, 0.f, 0.f, 0.f, 0.f, 1.f, 1.f, (__bf16 *)w.w, w.b, 0);
+           GW_TAIL_NPARAM, 0.f, 0.f, 0.f, 0.f, (const int *)nullptr, (__bf16 *)w.w, w.b, 0);
   return hipSuccess;
 }
 
@@ -428,9 +557,36 @@ hipError_t tail_apply(const gw_mlp &w, const float *feat, const float2 *p, int n
   const TailWs t = carve(ws, n);
   hipError_t e = forward(w, feat, n, t, t.o, s);
   if (e != hipSuccess) return e;
-  T_LAUNCH(tail_head_kernel, n, t.o, feat, n, t.d, t.u);
+  T_LAUNCH(tail_head_kernel, n, t.o, feat, n, w.rank, t.d, t.u);
   T_LAUNCH(tail_apply_kernel, (size_t)n * n, p, t.d, t.u, n, out);
   return hipSuccess;
+}
+
+hipError_t tail_residual_parts(const gw_mlp &w, const float *feat, const float2 *target, int n, float *ws,
+                               float *parts, hipStream_t s) {
+  const TailWs t = carve(ws, n);
+  hipError_t e = forward(w, feat, n, t, t.o, s);
+  if (e != hipSuccess) return e;
+  T_LAUNCH(tail_head_kernel, n, t.o, feat, n, w.rank, t.d, t.u);
+  hipLaunchKernelGGL(tail_parts_kernel, dim3(n), dim3(256), 0, s, t.d, t.u, target, n, t.part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(tail_parts_sum_kernel, dim3(1), dim3(256), 0, s, t.part, n, parts);
+  return hipGetLastError();
+}
+
+hipError_t tail_fit_norm(int nsys, const float *const *feats, const int *ngs, double *acc, float *norm,
+                         hipStream_t s) {
+  double total = 0.0;
+  for (int i = 0; i < nsys; ++i) total += ngs[i];
+  for (int pass = 0; pass < 2; ++pass)
+    for (int i = 0; i < nsys; ++i) {
+      hipLaunchKernelGGL(tail_stats_kernel, dim3(1), dim3(256), 0, s, feats[i], ngs[i], pass, i == 0 ? 1 : 0, total,
+                         acc);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  hipLaunchKernelGGL(tail_stats_final_kernel, dim3(1), dim3(64), 0, s, (const double *)acc, total, norm);
+  return hipGetLastError();
 }
 
 }  // namespace gwi

@@ -15,7 +15,7 @@ from oracle import sigma_oracle as so
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-ROWS = np.array([0, 1, 777, 23328, 46655])         # first, second, interior, centre, last grid point
+ROWS = np.array([0, 1, 127, 128, 777, 23328, 46591, 46592, 46655])   # first points, both sides of a tile edge, centre, the last (partial) tile
 GSEL = np.array([0, 1, 6, 100, 2033, 4066])
 
 

@@ -39,6 +39,21 @@ def test_small_grids_full(gw, n, r2, nb):
     assert e < 1e-6
 
 
+@pytest.mark.parametrize("n", [(24, 5, 6), (6, 24, 5), (5, 6, 24), (32, 5, 6), (6, 32, 5), (5, 6, 32),
+                               (36, 5, 6), (6, 36, 5), (5, 6, 36)])
+def test_long_axes(gw, n):
+    """Lengths 24, 32 and 36 on every axis, through the gather direction (sphere to grid)."""
+    rng = np.random.default_rng(sum(n) + 1)
+    mp = gs.sphere(n, r2=30.0)
+    nb = 70
+    c = (rng.standard_normal((nb, len(mp))) + 1j * rng.standard_normal((nb, len(mp)))).astype(np.complex64)
+    psi = gw.orbitals_to_grid(c64(c), n, mp).cpu().numpy()
+    ref = orc.orbitals_on_grid(c.astype(np.complex128), mp, n)
+    e = orc.rel_f(psi, ref)
+    print(f"{n} npw={len(mp)} nb={nb}: rel_F {e:.2e}")
+    assert e < 1e-6
+
+
 def test_production_orbitals_36(gw):
     """The 36^3 set of the full-size build: 128 + 1024 bands on the 4067-vector sphere."""
     s = gs.make_system(36, 128, 1024, r2_psi=98.0, seed=0)

@@ -102,6 +102,71 @@ def test_sphere_transform(gw, n, r2, q):
     assert e < 2e-6
 
 
+# Each long transform length (24 = 4 x 6, 32 = 4 x 8, 36 = 6 x 6) on every axis of a grid small enough
+# for the dense oracle, pruned to a sphere at q = 0 and unpruned (every non-Nyquist vector) at q != 0.
+LONG_GRIDS = [(L, 5, 6) for L in (24, 32, 36)] + [(6, L, 5) for L in (24, 32, 36)] + [(5, 6, L) for L in (24, 32, 36)]
+
+
+@pytest.mark.parametrize("n", LONG_GRIDS)
+@pytest.mark.parametrize("r2,q", [(20.0, (0.0, 0.0, 0.0)), (1e9, (0.15, -0.05, 0.3))])
+def test_sphere_transform_long_axes(gw, n, r2, q):
+    rng = np.random.default_rng(sum(n))
+    nr = n[0] * n[1] * n[2]
+    a = (rng.standard_normal((nr, nr)) + 1j * rng.standard_normal((nr, nr))).astype(np.complex64)
+    mill = gs.sphere(n, r2=r2, q=q)
+    print(f"[case] n={n} ng={len(mill)} q={q}", flush=True)
+    out = gw.sphere_transform(dev(a), n, mill)
+    torch.cuda.synchronize()
+    ref = orc.to_sphere(a.astype(np.complex128), n, mill)
+    e = orc.rel_f(out.cpu().numpy(), ref)
+    print(f"rel_F = {e:.3e}")
+    assert e < 2e-6
+
+
+# Grids with n2 = n3 take the row-contiguous transform (one wave per (row, i1) plane, then the i1 axis per
+# row); every other grid the strided passes.  Both the general form and the Hermitian form, which reads
+# only the upper triangle of P, are checked against the dense oracle, at q = 0 with a pruned sphere and at
+# q != 0 with every non-Nyquist vector.
+PLANE_GRIDS = [(5, 24, 24), (6, 32, 32), (4, 36, 36), (12, 12, 12), (9, 8, 8), (10, 5, 5)]
+
+
+def hermitian_c64(nr, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((nr, nr)) + 1j * rng.standard_normal((nr, nr))
+    h = (a + a.conj().T).astype(np.complex64)
+    iu = np.triu_indices(nr, 1)
+    h.T[iu] = np.conj(h[iu])                # exactly Hermitian after the rounding
+    h[np.diag_indices(nr)] = h[np.diag_indices(nr)].real
+    return h
+
+
+@pytest.mark.parametrize("n", PLANE_GRIDS)
+@pytest.mark.parametrize("r2,q", [(20.0, (0.0, 0.0, 0.0)), (1e9, (0.15, -0.05, 0.3))])
+def test_sphere_transform_plane_path(gw, n, r2, q):
+    nr = n[0] * n[1] * n[2]
+    mill = gs.sphere(n, r2=r2, q=q)
+    print(f"[case] plane path n={n} ng={len(mill)} q={q}", flush=True)
+    h = hermitian_c64(nr, sum(n))
+    rng = np.random.default_rng(sum(n) + 3)
+    a = (rng.standard_normal((nr, nr)) + 1j * rng.standard_normal((nr, nr))).astype(np.complex64)
+    out_g = gw.sphere_transform(dev(a), n, mill)
+    out_h = gw.sphere_transform(dev(h), n, mill, hermitian=True)
+    # below the diagonal the Hermitian form must read nothing: garbage there changes no output bit
+    hg = h.copy()
+    hg[np.tril_indices(nr, -1)] = 1e30
+    out_hg = gw.sphere_transform(dev(hg), n, mill, hermitian=True)
+    torch.cuda.synchronize()
+    ref_g = orc.to_sphere(a.astype(np.complex128), n, mill)
+    ref_h = orc.to_sphere(h.astype(np.complex128), n, mill)
+    e_g = orc.rel_f(out_g.cpu().numpy(), ref_g)
+    got_h = out_h.cpu().numpy()
+    e_h = orc.rel_f(got_h, ref_h)
+    print(f"general rel_F = {e_g:.3e}, hermitian rel_F = {e_h:.3e}")
+    assert e_g < 2e-6 and e_h < 2e-6
+    assert np.array_equal(got_h, out_hg.cpu().numpy())
+    assert np.array_equal(got_h, got_h.conj().T)              # X + X^H is Hermitian exactly
+
+
 # --- the whole build to P~ -----------------------------------------------------------------------
 @pytest.mark.parametrize("n,nv,nc,r2,q", [(12, 8, 64, 10.0, (0, 0, 0)), (8, 4, 20, 6.0, (0.0, 0.0, 0.001))])
 def test_polarizability_end_to_end(gw, n, nv, nc, r2, q):

@@ -122,6 +122,75 @@ def test_features_target_and_correction(gw):
     assert fb2 and corr2 is None
 
 
+def test_reduced_rank_correction_gradient_and_parts(gw):
+    """rank 5: the correction, the gradient and the residual parts against the oracle at the same rank."""
+    x, norm, t = random_case(n=301, seed=5)
+    master = gs.mlp_init(3)
+    model = gw.TailModel(master, norm, rank=5)
+    fx, ft = dev(x), dev(t)
+    params = oracle_params(master)
+    mean, std = norm[:4].astype(np.float64), norm[4:8].astype(np.float64)
+    o, cache = mo.forward(x.astype(np.float64), params, mean, std)
+    s = np.exp(x[:, 1].astype(np.float64))
+    p0 = np.zeros((301, 301), np.complex64)
+    corr, fb = model.correct(dev(p0), fx)
+    assert not fb
+    ref = mo.correction(o, s, rank=5)
+    e = orc.rel_f(corr.cpu().numpy(), ref)
+    assert e < 1e-5, e
+    parts = model.residual_parts(fx, ft).cpu().numpy().astype(np.float64)
+    parts_ref = np.array(mo.residual_parts(o, s, t.astype(np.complex128), rank=5))
+    print(f"rank 5: correction rel_F {e:.2e}, parts {parts} vs {parts_ref}")
+    assert np.max(np.abs(parts - parts_ref) / parts_ref) < 1e-4
+    model.train_step(fx, ft)
+    torch.cuda.synchronize()
+    g_ref = mo.flatten(mo.backward(mo.loss_grad_o(o, s, t.astype(np.complex128), rank=5), params, cache))
+    g = model.grad.cpu().numpy().astype(np.float64)
+    assert orc.rel_f(g, g_ref) < 1e-4
+    # outputs of unused columns get exactly zero gradient: the W3 columns 6..16 and 22..32
+    w3 = g[640 + 16384 + 128:640 + 16384 + 128 + 128 * 33].reshape(128, 33)
+    assert np.all(w3[:, 6:17] == 0) and np.all(w3[:, 22:] == 0)
+
+
+def test_fit_norm_matches_oracle(gw):
+    rng = np.random.default_rng(12)
+    feats = [np.stack([rng.uniform(0.2, 3.0, n), rng.uniform(-14, -6, n), np.full(n, 0.05 * (i + 1)),
+                       np.full(n, 0.3)], axis=1).astype(np.float32) for i, n in enumerate((925, 700, 1))]
+    got = gw.tail_fit_norm([dev(f) for f in feats]).cpu().numpy()
+    ref = mo.fit_norm(feats)
+    print("fit_norm", got, ref)
+    np.testing.assert_allclose(got, ref, rtol=1e-6)
+    assert got[7] == 1.0                       # E_max is constant over the set
+
+
+def test_graph_training_equals_eager_steps(gw):
+    """gw_tail_train_steps (graph replays) performs exactly the eager steps: same losses, same master
+    weights and moments, bit for bit; a second epoch in another order captures no new graph."""
+    cases = [random_case(n=n, seed=20 + i) for i, n in enumerate((150, 97, 150))]
+    norm = cases[0][1]
+    feats = [dev(c[0]) for c in cases]
+    targets = [dev(c[2]) for c in cases]
+    eager = gw.TailModel(gs.mlp_init(4), norm, lr=1e-3)
+    graph = gw.TailModel(gs.mlp_init(4), norm, lr=1e-3)
+    orders = [[2, 0, 1], [1, 2, 0, 0]]
+    le = torch.zeros(3, dtype=torch.float32, device="cuda:0")
+    lg = torch.zeros(3, dtype=torch.float32, device="cuda:0")
+    ctx = graph.ctx
+    for ep, order in enumerate(orders):
+        for j in order:
+            eager.train_step(feats[j], targets[j], loss_out=le[j:j + 1])
+        graph.train_steps(feats, targets, order, lg)
+        torch.cuda.synchronize()
+        assert torch.equal(le, lg), (le, lg)
+        if ep == 0:
+            n_graphs = gw.load().gw_tail_graph_count(ctx.handle)
+            assert n_graphs >= 3
+    assert gw.load().gw_tail_graph_count(ctx.handle) == n_graphs
+    assert eager.step == graph.step == 7
+    for a, b in ((eager.master, graph.master), (eager.m, graph.m), (eager.v, graph.v), (eager.w, graph.w)):
+        assert torch.equal(a, b)
+
+
 @pytest.mark.timeout(900)
 def test_training_and_gain_on_larger_systems(gw):
     """Train on 200 seeded 16^3 systems (Nc in {64, 96, 128}, each against 4 Nc; 180 train, 20 validation),
@@ -138,8 +207,10 @@ def test_training_and_gain_on_larger_systems(gw):
             print(f"[case] training system {k}", flush=True)
     train_e, val_e = entries[:180], entries[180:]
     norm = tail.fit_norm([e["feat"] for e in train_e])
-    model = gw.TailModel(gs.mlp_init(0), norm, lr=3e-4)
-    hist = tail.train(model, train_e, 60, val=val_e, log=lambda m: print(m, flush=True) if "0/" in m else None)
+    # the rank of the U U^H term is chosen on the validation systems among 16 and 0
+    model, hist, report = tail.train_select_rank(gs.mlp_init(0), norm, train_e, val_e, 60, lr=3e-4,
+                                                 log=lambda m: print(m, flush=True) if ("0/" in m or "rank" in m) else None)
+    print(f"selected rank {model.rank}; validation parts {report}")
     assert hist[-1][1] < 0.5 * hist[0][1], hist
     gains = []
     for k in range(8):
@@ -163,4 +234,5 @@ def test_training_and_gain_on_larger_systems(gw):
     for row in gains:
         assert row["full"][1] < row["full"][0]
         assert row["diag"][1] < 0.5 * row["diag"][0]
+        assert row["offdiag"][1] <= row["offdiag"][0]
         assert row["eps_inv"][1] < 0.5 * row["eps_inv"][0]

@@ -159,3 +159,60 @@ def test_head_hand_values():
     assert u[0, 0] == 6.0 - 8.0j and u[0, 15] == 1.0 + 0.5j and np.all(u[0, 1:15] == 0)
     # the correction is -(d + |u|^2) on the diagonal: -(4 log 2 + 100 + 1.25)
     np.testing.assert_allclose(mo.correction(o, s), [[-(2.77258872223978123766892848583 + 101.25)]], rtol=1e-15)
+
+
+def test_rank_zero_correction_is_diagonal_and_rank_masks_columns():
+    params, x, mean, std, t, s = small_case(n=6, seed=8)
+    o, _ = mo.forward(x, params, mean, std)
+    c0 = mo.correction(o, s, rank=0)
+    assert np.array_equal(c0, np.diag(np.diag(c0)))
+    np.testing.assert_allclose(np.diag(c0).real, -mo.softplus(o[:, 0]) * s, rtol=1e-15)
+    # rank 3: exactly the first three columns of U, by an explicit sum
+    d, u = mo.head(o, s)
+    want = -(np.diag(d) + sum(np.outer(u[:, k], np.conj(u[:, k])) for k in range(3)))
+    assert np.max(np.abs(mo.correction(o, s, rank=3) - want)) <= 1e-15 * np.abs(want).max()
+
+
+def test_residual_parts_elementwise():
+    params, x, mean, std, t, s = small_case(n=5, seed=6)
+    o, _ = mo.forward(x, params, mean, std)
+    for rank in (16, 2, 0):
+        d, u = mo.head(o, s)
+        parts = [0.0, 0.0, 0.0, 0.0]
+        for i in range(5):
+            for j in range(5):
+                corr = -((d[i] if i == j else 0.0) + sum(u[i, k] * np.conj(u[j, k]) for k in range(rank)))
+                k = 2 if i == j else 0
+                parts[k] += abs(corr - t[i, j]) ** 2
+                parts[k + 1] += abs(t[i, j]) ** 2
+        got = mo.residual_parts(o, s, t, rank)
+        np.testing.assert_allclose(got, parts, rtol=1e-12)
+        assert abs((got[0] + got[2]) / (got[1] + got[3]) - mo.loss(o, s, t, rank)) <= 1e-12 * mo.loss(o, s, t, rank)
+
+
+def test_grad_o_finite_differences_reduced_rank():
+    params, x, mean, std, t, s = small_case(seed=11)
+    o, _ = mo.forward(x, params, mean, std)
+    g = mo.loss_grad_o(o, s, t, rank=5)
+    assert np.all(g[:, 6:17] == 0) and np.all(g[:, 22:] == 0)
+    rng = np.random.default_rng(2)
+    h = 1e-6
+    for _ in range(25):
+        i, j = rng.integers(o.shape[0]), rng.integers(o.shape[1])
+        op, om = o.copy(), o.copy()
+        op[i, j] += h
+        om[i, j] -= h
+        fd = (mo.loss(op, s, t, 5) - mo.loss(om, s, t, 5)) / (2 * h)
+        assert abs(fd - g[i, j]) <= 1e-6 * max(1.0, abs(fd)), (i, j, fd, g[i, j])
+
+
+def test_fit_norm_hand_values():
+    a = np.array([[1.0, 2.0, 0.5, 3.0], [3.0, 2.0, 0.5, 3.0]])
+    b = np.array([[5.0, 2.0, 0.5, 3.0]])
+    nm = mo.fit_norm([a, b])
+    # feature 0: values 1, 3, 5 -> mean 3, population std sqrt(8/3); the constant features get std 1
+    np.testing.assert_allclose(nm[:4], [3.0, 2.0, 0.5, 3.0], rtol=1e-7)
+    np.testing.assert_allclose(nm[4:8], [1.632993161855452, 1.0, 1.0, 1.0], rtol=1e-7)
+    np.testing.assert_array_equal(nm[8:12], [1.0, 2.0, 0.5, 3.0])
+    np.testing.assert_array_equal(nm[12:], [5.0, 2.0, 0.5, 3.0])
+    assert nm.dtype == np.float32
