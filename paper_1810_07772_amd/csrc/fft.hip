@@ -69,26 +69,6 @@ struct Twiddle {
   }
 };
 
-// factor choice R1 * R2 = N with both factors small
-template <int N> struct Factor { static constexpr int R1 = N, R2 = 1; };
-template <> struct Factor<4> { static constexpr int R1 = 2, R2 = 2; };
-template <> struct Factor<6> { static constexpr int R1 = 2, R2 = 3; };
-template <> struct Factor<8> { static constexpr int R1 = 2, R2 = 4; };
-template <> struct Factor<9> { static constexpr int R1 = 3, R2 = 3; };
-template <> struct Factor<10> { static constexpr int R1 = 2, R2 = 5; };
-template <> struct Factor<12> { static constexpr int R1 = 3, R2 = 4; };
-template <> struct Factor<15> { static constexpr int R1 = 3, R2 = 5; };
-template <> struct Factor<16> { static constexpr int R1 = 4, R2 = 4; };
-template <> struct Factor<18> { static constexpr int R1 = 3, R2 = 6; };
-template <> struct Factor<20> { static constexpr int R1 = 4, R2 = 5; };
-template <> struct Factor<24> { static constexpr int R1 = 4, R2 = 6; };
-template <> struct Factor<27> { static constexpr int R1 = 3, R2 = 9; };
-template <> struct Factor<30> { static constexpr int R1 = 5, R2 = 6; };
-template <> struct Factor<32> { static constexpr int R1 = 4, R2 = 8; };
-template <> struct Factor<36> { static constexpr int R1 = 6, R2 = 6; };
-template <> struct Factor<40> { static constexpr int R1 = 5, R2 = 8; };
-template <> struct Factor<48> { static constexpr int R1 = 6, R2 = 8; };
-
 // acc += x * W^m with W^m = (c, sgn * s) a compile-time constant after unrolling.
 template <int N, int SIGN>
 __device__ __forceinline__ void cmac_tw(float2 &acc, float2 x, int m) {
@@ -118,61 +98,128 @@ __device__ __forceinline__ float2 mul_tw(float2 x, int m) {
   return acc;
 }
 
-// In-register DFT X[k] = sum_n x[n] exp(SIGN * 2 pi i n k / N), n = R2*n1 + n2, k = k1 + R1*k2.
+// ---- in-register mixed-radix FFT ----------------------------------------------------------------
+// X[k] = sum_n x[n] W^{n k}, W = exp(SIGN 2 pi i / N), by recursive Cooley-Tukey: N = R M with the radix R
+// taken from 4, 3, 2, 5 in that order of preference; n = M n1 + n2, k = k1 + R k2:
+//   y[k1][n2] = W_N^{n2 k1} sum_{n1} x[M n1 + n2] W_R^{n1 k1},   X[k1 + R k2] = sum_{n2} y[k1][n2] W_M^{n2 k2}.
+// The R-point DFTs are written-out butterflies (radix 4 and 2 need only additions, radix 3 one real
+// multiplication pair), the twiddles are compile-time constants (trivial ones skipped by mul_tw), and
+// the M-point DFTs recurse.
+template <int N> struct Radix { static constexpr int R = (N % 4 == 0) ? 4 : (N % 3 == 0) ? 3 : (N % 2 == 0) ? 2 : N; };
+
+template <int R, int SIGN> struct Butterfly;
+template <int SIGN> struct Butterfly<2, SIGN> {
+  static __device__ __forceinline__ void run(float2 (&v)[2]) {
+    const float2 a = v[0], b = v[1];
+    v[0] = make_float2(a.x + b.x, a.y + b.y);
+    v[1] = make_float2(a.x - b.x, a.y - b.y);
+  }
+};
+template <int SIGN> struct Butterfly<4, SIGN> {
+  // X1 = (a - c) + SIGN i (b - d), X3 = (a - c) - SIGN i (b - d)
+  static __device__ __forceinline__ void run(float2 (&v)[4]) {
+    const float2 a = v[0], b = v[1], c = v[2], d = v[3];
+    const float2 s0 = make_float2(a.x + c.x, a.y + c.y), d0 = make_float2(a.x - c.x, a.y - c.y);
+    const float2 s1 = make_float2(b.x + d.x, b.y + d.y), d1 = make_float2(b.x - d.x, b.y - d.y);
+    const float2 r = SIGN > 0 ? make_float2(-d1.y, d1.x) : make_float2(d1.y, -d1.x);   // SIGN i (b - d)
+    v[0] = make_float2(s0.x + s1.x, s0.y + s1.y);
+    v[2] = make_float2(s0.x - s1.x, s0.y - s1.y);
+    v[1] = make_float2(d0.x + r.x, d0.y + r.y);
+    v[3] = make_float2(d0.x - r.x, d0.y - r.y);
+  }
+};
+template <int SIGN> struct Butterfly<3, SIGN> {
+  // X1,2 = a - (b + c)/2 +- SIGN i (sqrt(3)/2) (b - c)
+  static __device__ __forceinline__ void run(float2 (&v)[3]) {
+    constexpr float h = 0.866025403784438646763723170752936f;   // sqrt(3)/2
+    const float2 a = v[0], b = v[1], c = v[2];
+    const float2 t = make_float2(b.x + c.x, b.y + c.y), d = make_float2(b.x - c.x, b.y - c.y);
+    const float2 m = make_float2(a.x - 0.5f * t.x, a.y - 0.5f * t.y);
+    const float2 r = SIGN > 0 ? make_float2(-h * d.y, h * d.x) : make_float2(h * d.y, -h * d.x);
+    v[0] = make_float2(a.x + t.x, a.y + t.y);
+    v[1] = make_float2(m.x + r.x, m.y + r.y);
+    v[2] = make_float2(m.x - r.x, m.y - r.y);
+  }
+};
+template <int R, int SIGN> struct Butterfly {   // any other radix (5): the plain DFT with constant twiddles
+  static __device__ __forceinline__ void run(float2 (&v)[R]) {
+    float2 o[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int n = 0; n < R; ++n) cmac_tw<R, SIGN>(acc, v[n], n * k % R);
+      o[k] = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] = o[k];
+  }
+};
+
+template <int N, int SIGN> struct Fft {
+  static __device__ __forceinline__ void run(float2 (&x)[N]) {
+    constexpr int R = Radix<N>::R, M = N / R;
+    if constexpr (M == 1) {
+      Butterfly<N, SIGN>::run(x);
+    } else {
+      float2 y[R][M];
+#pragma unroll
+      for (int n2 = 0; n2 < M; ++n2) {
+        float2 v[R];
+#pragma unroll
+        for (int n1 = 0; n1 < R; ++n1) v[n1] = x[M * n1 + n2];
+        Butterfly<R, SIGN>::run(v);
+#pragma unroll
+        for (int k1 = 0; k1 < R; ++k1) y[k1][n2] = (n2 * k1 == 0) ? v[k1] : mul_tw<N, SIGN>(v[k1], n2 * k1);
+      }
+#pragma unroll
+      for (int k1 = 0; k1 < R; ++k1) {
+        Fft<M, SIGN>::run(y[k1]);
+#pragma unroll
+        for (int k2 = 0; k2 < M; ++k2) x[k1 + R * k2] = y[k1][k2];
+      }
+    }
+  }
+};
+
+// In-register DFT X = DFT_N(x) (sign SIGN), by the mixed-radix FFT above.
 template <int N, int SIGN>
 __device__ __forceinline__ void dft_regs(const float2 (&x)[N], float2 (&X)[N]) {
-  constexpr int R1 = Factor<N>::R1, R2 = Factor<N>::R2;
-  float2 y[R1][R2];
 #pragma unroll
-  for (int n2 = 0; n2 < R2; ++n2)
-#pragma unroll
-    for (int k1 = 0; k1 < R1; ++k1) {
-      float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int n1 = 0; n1 < R1; ++n1) cmac_tw<N, SIGN>(acc, x[R2 * n1 + n2], (n1 * k1 % R1) * R2);
-      y[k1][n2] = (n2 * k1 == 0) ? acc : mul_tw<N, SIGN>(acc, n2 * k1);
-    }
-#pragma unroll
-  for (int k1 = 0; k1 < R1; ++k1)
-#pragma unroll
-    for (int k2 = 0; k2 < R2; ++k2) {
-      float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int n2 = 0; n2 < R2; ++n2) cmac_tw<N, SIGN>(acc, y[k1][n2], (n2 * k2 % R2) * R1);
-      X[k1 + R1 * k2] = acc;
-    }
+  for (int n = 0; n < N; ++n) X[n] = x[n];
+  Fft<N, SIGN>::run(X);
 }
 
-// The same DFT with its inputs read through ld(n) one first-stage group at a time: the R1 inputs
-// x[R2 n1 + n2] of one n2 are loaded, combined and dropped before the next group's loads, so at most
-// R1 inputs and the N partial results are live (the plain form keeps all N inputs as well).
+// The same FFT with its inputs read through ld(n) one first-stage group at a time: the R inputs
+// x[M n1 + n2] of one n2 are loaded, combined and twiddled before the next group's loads (a scheduling
+// barrier keeps the compiler from issuing every load at once), so at most R inputs and the N partial
+// results are live.
 template <int N, int SIGN, typename Load>
 __device__ __forceinline__ void dft_regs_load(Load ld, float2 (&X)[N]) {
-  constexpr int R1 = Factor<N>::R1, R2 = Factor<N>::R2;
-  float2 y[R1][R2];
+  constexpr int R = Radix<N>::R, M = N / R;
+  if constexpr (M == 1) {
 #pragma unroll
-  for (int n2 = 0; n2 < R2; ++n2) {
-    float2 xs[R1];
+    for (int n = 0; n < N; ++n) X[n] = ld(n);
+    Butterfly<N, SIGN>::run(X);
+  } else {
+    float2 y[R][M];
 #pragma unroll
-    for (int n1 = 0; n1 < R1; ++n1) xs[n1] = ld(R2 * n1 + n2);
+    for (int n2 = 0; n2 < M; ++n2) {
+      float2 v[R];
 #pragma unroll
-    for (int k1 = 0; k1 < R1; ++k1) {
-      float2 acc = make_float2(0.f, 0.f);
+      for (int n1 = 0; n1 < R; ++n1) v[n1] = ld(M * n1 + n2);
+      Butterfly<R, SIGN>::run(v);
 #pragma unroll
-      for (int n1 = 0; n1 < R1; ++n1) cmac_tw<N, SIGN>(acc, xs[n1], (n1 * k1 % R1) * R2);
-      y[k1][n2] = (n2 * k1 == 0) ? acc : mul_tw<N, SIGN>(acc, n2 * k1);
+      for (int k1 = 0; k1 < R; ++k1) y[k1][n2] = (n2 * k1 == 0) ? v[k1] : mul_tw<N, SIGN>(v[k1], n2 * k1);
+      if (n2 + 1 < M) __builtin_amdgcn_sched_barrier(0);
     }
-    if (n2 + 1 < R2) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) {
+      Fft<M, SIGN>::run(y[k1]);
+#pragma unroll
+      for (int k2 = 0; k2 < M; ++k2) X[k1 + R * k2] = y[k1][k2];
+    }
   }
-#pragma unroll
-  for (int k1 = 0; k1 < R1; ++k1)
-#pragma unroll
-    for (int k2 = 0; k2 < R2; ++k2) {
-      float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int n2 = 0; n2 < R2; ++n2) cmac_tw<N, SIGN>(acc, y[k1][n2], (n2 * k2 % R2) * R1);
-      X[k1 + R1 * k2] = acc;
-    }
 }
 
 constexpr int FFT_THREADS = 256;
@@ -369,96 +416,144 @@ hipError_t launch_fft_gather_pass_t(int n, int sign, const float2 *in, float2 *o
 // Hermitian P (P = M + M^H with M its upper triangle and half its real diagonal), only the upper
 // triangle is read (HERM): planes wholly left of the diagonal are skipped and read as zero.
 
-// One wave per (row r, plane i1); four waves per workgroup.  Lane i3 (< N) loads the plane's column i3
-// (N consecutive loads of N consecutive values: each load instruction reads 8 N contiguous bytes),
-// transforms it over i2 in registers, and leaves its N outputs k2 in the wave's LDS block [k2][i3].
-// Lane s (< nk2) then takes the row k2 = k2list[s], transforms it over i3 in registers, and stores the
-// outputs whose (k2, k3) is a sphere pair at that pair's slot; the wave finally writes the npair slots
-// to y1[r][i1][.] with contiguous stores.  One wave reads and writes its own LDS block only, in program
-// order, so no workgroup barrier is needed.
+// One wave (one workgroup) per row r and pl consecutive i1 planes of it.  Phase 1: item t < pl n3 is
+// column i3 = t % n3 of plane t / n3; its lane loads the column (n2 loads, each wave instruction reading
+// runs of 8 n3 contiguous bytes), transforms it over i2 in registers and keeps the rows k2 that occur in
+// sphere pairs (slot k2s[k2] >= 0) in LDS [plane][slot][i3] (row stride n3 + 1 against bank conflicts).
+// Phase 2: item t < pl nk2 (one round: pl nk2 <= 64) is row slot t % nk2 of plane t / nk2; its lane
+// loads the row, transforms it over i3 and writes the outputs whose (k2, k3) is a sphere pair to LDS
+// [plane][pair], over the rows every lane has read.  The planes of one block are consecutive in y1, so
+// the block's output leaves in one contiguous run.  pl is chosen on the host to keep the lanes busy:
+// at n = 36 with 19 rows k2, three planes fill 108 of 128 lanes in phase 1 and 57 of 64 in phase 2.
 template <int N, bool HERM>
-__global__ __launch_bounds__(256) void plane_ab_kernel(const float2 *__restrict__ P, long long ldp, int nr, int n1,
-                                                       const int *__restrict__ k2list, int nk2,
-                                                       const int *__restrict__ mapab, int npair,
-                                                       float2 *__restrict__ y1) {
-  __shared__ float2 lds[4][N * N];
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int r = blockIdx.x * 4 + w, i1 = blockIdx.y;
-  constexpr int PL = N * N;
-  if (r >= nr) return;
-  const long long c0 = (long long)i1 * PL;
-  if (HERM && c0 + PL <= r) return;              // left of the diagonal: zero, never read downstream
-  float2 *L = lds[w];
-  if (lane < N) {
-    const float2 *src = P + (long long)r * ldp + c0 + lane;
-    float2 x[N], X[N];
+__global__ __launch_bounds__(64) void plane_ab_kernel(const float2 *__restrict__ P, long long ldp, int n1, int pl,
+                                                      const int *__restrict__ k2s, int nk2,
+                                                      const int *__restrict__ mapab, int npair,
+                                                      float2 *__restrict__ y1) {
+  constexpr int PLN = N * N, LD = N + 1;
+  extern __shared__ float2 lds[];                 // [pl][nk2][LD], then [pl][npair] over it
+  const int lane = threadIdx.x;
+  const int r = blockIdx.x, i10 = blockIdx.y * pl;
+  const int roff = r - i10 * PLN;                 // the diagonal's offset in the first plane of the block
+  const int pfirst = (HERM && roff >= 0) ? min(roff / PLN, pl) : 0;   // planes left of it hold no work
+  const int pend = min(pl, n1 - i10);
+  if (pfirst >= pend) return;
+  const int reg = nk2 * LD;
+  const bool diag = HERM && roff >= 0 && roff < pl * PLN;   // the diagonal lies in one of the block's planes
+  const float2 *src = P + (long long)r * ldp + (long long)i10 * PLN;
+  for (int t0 = 0; t0 < pl * N; t0 += 64) {
+    const int t = t0 + lane, p = t / N, i3 = t - p * N;
+    if (p >= pfirst && p < pend) {
+      const float2 *pln = src + (long long)p * PLN;
+      const int eo = roff - p * PLN;              // element offset of the diagonal in plane p
+      float2 x[N];
+      if (HERM && diag) {
+        // Lanes left of the diagonal load the diagonal element (finite) and scale it by 0: the value is
+        // used on every path, so each load stays unconditional and all of them are in flight at once.
 #pragma unroll
-    for (int i2 = 0; i2 < N; ++i2) {
-      float2 v = src[i2 * N];
-      if (HERM) {
-        const long long c = c0 + i2 * N + lane;
-        if (c < r) v = make_float2(0.f, 0.f);
-        else if (c == r) v = make_float2(0.5f * v.x, 0.f);     // M carries half the (real) diagonal
+        for (int i2 = 0; i2 < N; ++i2) {
+          const int e = i2 * N + i3;
+          const bool lo = e < eo, dg = e == eo;
+          float2 v = pln[lo ? eo : e];
+          v.x *= lo ? 0.f : dg ? 0.5f : 1.f;      // M carries half the (real) diagonal
+          v.y *= (lo || dg) ? 0.f : 1.f;
+          x[i2] = v;
+        }
+      } else {
+#pragma unroll
+        for (int i2 = 0; i2 < N; ++i2) x[i2] = pln[i2 * N + i3];
       }
-      x[i2] = v;
+      __builtin_amdgcn_sched_barrier(0);          // every load of the column in flight before the first use
+      Fft<N, 1>::run(x);
+      float2 *L = lds + p * reg + i3;
+#pragma unroll
+      for (int k2 = 0; k2 < N; ++k2) {
+        const int sl = k2s[k2];
+        if (sl >= 0) L[sl * LD] = x[k2];
+      }
     }
-    dft_regs<N, 1>(x, X);
-#pragma unroll
-    for (int k2 = 0; k2 < N; ++k2) L[k2 * N + lane] = X[k2];
   }
-  if (lane < nk2) {
-    const int k2 = k2list[lane];
-    float2 x[N], X[N];
+  __syncthreads();
+  const int p = lane / nk2, sl = lane - p * nk2;
+  const bool act = p >= pfirst && p < pend;
+  float2 x[N];
+  if (act) {
+    const float2 *row = lds + p * reg + sl * LD;
 #pragma unroll
-    for (int i3 = 0; i3 < N; ++i3) x[i3] = L[k2 * N + i3];
-    dft_regs<N, 1>(x, X);
-    const int *mrow = mapab + lane * N;
+    for (int i3 = 0; i3 < N; ++i3) x[i3] = row[i3];
+  }
+  __syncthreads();                                // every row is in registers: the region is free
+  if (act) {
+    Fft<N, 1>::run(x);
+    const int *mrow = mapab + sl * N;
+    float2 *out = lds + p * npair;
 #pragma unroll
     for (int k3 = 0; k3 < N; ++k3) {
       const int pid = mrow[k3];
-      if (pid >= 0) L[pid] = X[k3];                           // after every lane's reads (program order)
+      if (pid >= 0) out[pid] = x[k3];
     }
   }
-  float2 *dst = y1 + ((long long)r * n1 + i1) * npair;
-  for (int j = lane; j < npair; j += 64) dst[j] = L[j];
+  __syncthreads();
+  float2 *dst = y1 + ((long long)r * n1 + i10) * npair;
+  for (int j = pfirst * npair + lane; j < pend * npair; j += 64) dst[j] = lds[j];
+}
+
+// Planes per wave: the fewest wave rounds per plane over both phases, phase 2 in one round.
+static int plane_ab_planes(int n, int nk2, int n1) {
+  int best = 1;
+  double cost = 1e30;
+  for (int pl = 1; pl <= 8 && pl <= n1 && pl * nk2 <= 64; ++pl) {
+    const double c = double((pl * n + 63) / 64 + 1) / pl;
+    if (c < cost - 1e-9) cost = c, best = pl;
+  }
+  return best;
 }
 
 // One workgroup per row r: the i1 transform of every pair (lanes over pairs, loads contiguous across
 // lanes), each output k1 sent to its sphere vector through mapct [N1][npair] (-1: not on the sphere).
 // The row's ng outputs are staged in LDS and written contiguously when they fit (STAGE), else directly.
-constexpr int PLANE_C_STAGE = 8192;   // sphere vectors staged in LDS (64 KB)
+constexpr int PLANE_C_STAGE = 8191;   // sphere vectors staged in LDS (with the spare slot, 64 KB)
 template <int N1, bool HERM, bool STAGE>
-__global__ __launch_bounds__(256, 2) void plane_c_kernel(const float2 *__restrict__ y1, int plane, int npair,
+__global__ __launch_bounds__(512) void plane_c_kernel(const float2 *__restrict__ y1, int plane, int npair,
                                                       const int *__restrict__ mapct, int ng,
                                                       float2 *__restrict__ y, long long ldy) {
-  extern __shared__ float2 so[];
+  extern __shared__ float2 so[];                  // [ng + 1]: the sphere row, then a slot for unmapped outputs
   const int r = blockIdx.x;
   const int i1s = HERM ? r / plane : 0;          // planes left of the diagonal are zero
   const float2 *src = y1 + (long long)r * N1 * npair;
   float2 *yr = y + (long long)r * ldy;
+  constexpr int C = 6;                            // map reads per group
 #pragma unroll 1
-  for (int p = threadIdx.x; p < npair; p += 256) {
+  for (int p = threadIdx.x; p < npair; p += blockDim.x) {
     float2 X[N1];
     const float2 *sp = src + p;
     dft_regs_load<N1, 1>([&](int i1) { return i1 >= i1s ? sp[(long long)i1 * npair] : make_float2(0.f, 0.f); }, X);
-    // outputs in groups of six map reads: a scheduling barrier between groups keeps the compiler from
-    // issuing every map read at once (N1 more live registers, and spills at N1 = 36 and 48)
+    // The sphere index of each output comes from the map in groups of C reads, the next group in flight
+    // while the current one is stored: every read is waited for once per group, not once per output,
+    // and only 2 C map values are live at a time.
+    const int *mp = mapct + p;
+    int g[C], gn[C];
 #pragma unroll
-    for (int kc = 0; kc < N1; kc += 6) {
+    for (int j = 0; j < C; ++j) g[j] = j < N1 ? mp[j * npair] : -1;
+#pragma unroll
+    for (int kc = 0; kc < N1; kc += C) {
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int k1 = kc; k1 < (kc + 6 < N1 ? kc + 6 : N1); ++k1) {
-        const int g = mapct[k1 * npair + p];
-        if (g >= 0) {
-          if (STAGE) so[g] = X[k1];
-          else yr[g] = X[k1];
+      for (int j = 0; j < C; ++j) gn[j] = kc + C + j < N1 ? mp[(kc + C + j) * npair] : -1;
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        if (kc + j < N1) {
+          if (STAGE) so[g[j] >= 0 ? g[j] : ng] = X[kc + j];
+          else if (g[j] >= 0) yr[g[j]] = X[kc + j];
         }
       }
+#pragma unroll
+      for (int j = 0; j < C; ++j) g[j] = gn[j];
     }
   }
   if (STAGE) {
     __syncthreads();
-    for (int g = threadIdx.x; g < ng; g += 256) yr[g] = so[g];
+    for (int g = threadIdx.x; g < ng; g += blockDim.x) yr[g] = so[g];
   }
 }
 
@@ -483,19 +578,22 @@ __global__ __launch_bounds__(256) void add_adjoint_kernel(const float2 *__restri
 
 bool plane_path_supported(int n2, int n3) { return n2 == n3 && n3 <= 64 && fft_size_supported(n3); }
 
-hipError_t launch_plane_ab(int n, bool herm, const float2 *p, long long ldp, int nr, int n1, const int *k2list, int nk2,
+hipError_t launch_plane_ab(int n, bool herm, const float2 *p, long long ldp, int nr, int n1, const int *k2s, int nk2,
                            const int *mapab, int npair, float2 *y1, hipStream_t s) {
-  if (n1 > 65535 || nk2 > 64 || nk2 > n) return hipErrorInvalidValue;
-  dim3 grid((nr + 3) / 4, n1), block(256);
+  if (nk2 < 1 || nk2 > n || nk2 > 64 || npair > nk2 * n) return hipErrorInvalidValue;
+  const int pl = plane_ab_planes(n, nk2, n1);
+  dim3 grid(nr, (n1 + pl - 1) / pl), block(64);
+  const size_t shm = (size_t)pl * nk2 * (n + 1) * sizeof(float2);
+  if (grid.y > 65535 || shm > 64 * 1024) return hipErrorInvalidValue;
   switch (n) {
-#define GW_CASE(n_)                                                                                               \
-  case n_:                                                                                                        \
-    if (herm)                                                                                                     \
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(plane_ab_kernel<n_, true>), grid, block, 0, s, p, ldp, nr, n1, k2list, nk2, \
-                         mapab, npair, y1);                                                                      \
-    else                                                                                                          \
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(plane_ab_kernel<n_, false>), grid, block, 0, s, p, ldp, nr, n1, k2list, nk2, \
-                         mapab, npair, y1);                                                                      \
+#define GW_CASE(n_)                                                                                                  \
+  case n_:                                                                                                           \
+    if (herm)                                                                                                        \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(plane_ab_kernel<n_, true>), grid, block, shm, s, p, ldp, n1, pl, k2s, nk2,   \
+                         mapab, npair, y1);                                                                          \
+    else                                                                                                             \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(plane_ab_kernel<n_, false>), grid, block, shm, s, p, ldp, n1, pl, k2s, nk2,  \
+                         mapab, npair, y1);                                                                          \
     break;
     GW_FFT_SIZES(GW_CASE)
 #undef GW_CASE
@@ -507,8 +605,9 @@ hipError_t launch_plane_ab(int n, bool herm, const float2 *p, long long ldp, int
 hipError_t launch_plane_c(int n1, bool herm, const float2 *y1, int nr, int plane, int npair, const int *mapct, int ng,
                           float2 *y, long long ldy, hipStream_t s) {
   const bool stage = ng <= PLANE_C_STAGE;
-  const size_t shm = stage ? (size_t)ng * sizeof(float2) : 0;
-  dim3 grid(nr), block(256);
+  const size_t shm = stage ? (size_t)(ng + 1) * sizeof(float2) : 0;
+  // one thread per pair where that fits in 512 threads: a block of whole waves covering npair
+  dim3 grid(nr), block(std::min(512, std::max(64, (npair + 63) / 64 * 64)));
   switch (n1) {
 #define GW_CASE(n_)                                                                                              \
   case n_:                                                                                                       \

@@ -229,6 +229,8 @@ void build_sphere_plan(gw_grid g, const int *miller, int ng, SpherePlan &p) {
       if (any) p.mapK2.push_back(k2);
     }
     p.nk2 = (int)p.mapK2.size();
+    p.mapK2.resize((size_t)p.nk2 + g.n2, -1);                  // then the slot of each k2 (-1: no pair)
+    for (int sl = 0; sl < p.nk2; ++sl) p.mapK2[(size_t)p.nk2 + p.mapK2[sl]] = sl;
     p.mapAB.assign((size_t)p.nk2 * g.n3, -1);
     for (int sl = 0; sl < p.nk2; ++sl)
       for (int k3 = 0; k3 < g.n3; ++k3)
@@ -262,7 +264,8 @@ hipError_t enqueue_sphere_transform(const SpherePlan &p, const SphereBuffers &b,
   if (p.plane && b.y1) {
     // rows of M (P itself, or for a Hermitian P its upper triangle with half the diagonal), contiguous:
     // Y[r][g'] = sum_r' M(r, r') exp(+i G'.r')
-    if ((e = launch_plane_ab(p.n3, herm, p_rr, nr, nr, p.n1, b.dK2, p.nk2, b.dAB, p.npair, b.y1, s)) != hipSuccess)
+    if ((e = launch_plane_ab(p.n3, herm, p_rr, nr, nr, p.n1, b.dK2 + p.nk2, p.nk2, b.dAB, p.npair, b.y1, s)) !=
+        hipSuccess)
       return e;
     if ((e = launch_plane_c(p.n1, herm, b.y1, nr, p.n2 * p.n3, p.npair, b.dCT, ng, b.ph, ng, s)) != hipSuccess)
       return e;

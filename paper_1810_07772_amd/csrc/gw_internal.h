@@ -196,7 +196,7 @@ struct SpherePlan {
   // row-contiguous form (plane_ab_kernel / plane_c_kernel; only when n2 == n3, see plane_path_supported)
   bool plane = false;
   int nk2 = 0;                     // k2 values that occur in a sphere pair
-  std::vector<int> mapK2;          // [nk2] those k2 (grid indices 0 .. n2-1)
+  std::vector<int> mapK2;          // [nk2] those k2 (grid indices 0 .. n2-1), then [n2] the slot of each k2 or -1
   std::vector<int> mapAB;          // [nk2][n3] pair slot of (k2, k3) or -1
   std::vector<int> mapCT;          // [n1][npair] sphere index of (k1, pair) or -1
   size_t y1_elems = 0;             // [nr][n1][npair] intermediate
@@ -214,7 +214,7 @@ struct SphereBuffers {
   float2 *a1, *a2, *ph, *pht, *q;  // pass intermediates, P^ [ng][nr], its transpose, Q [ng][ng]
   const int *dA, *dB, *dC;         // device copies of the plan's maps
   float2 *y1 = nullptr;            // row-contiguous form: [nr][n1][npair] (plan.y1_elems)
-  const int *dK2 = nullptr, *dAB = nullptr, *dCT = nullptr;
+  const int *dK2 = nullptr, *dAB = nullptr, *dCT = nullptr;   // dK2: the k2 list, then the slot table
 };
 // P~ from P(r,r') [nr][nr].  herm: P is Hermitian (as the update writes it), so only its upper
 // triangle is read.  The row-contiguous form runs where the plan allows it (b.y1 set), else the
@@ -225,7 +225,7 @@ bool plane_path_supported(int n2, int n3);
 // Whether the triangle (Hermitian) form of the transforms suits a build at q with this sphere: no vector
 // with 0 < |q+m| < 1e-2 (crystal units), whose Coulomb factor would amplify that form's head-row rounding.
 bool triangle_form_suits(const double *q, const int *miller, int ng);
-hipError_t launch_plane_ab(int n, bool herm, const float2 *p, long long ldp, int nr, int n1, const int *k2list, int nk2,
+hipError_t launch_plane_ab(int n, bool herm, const float2 *p, long long ldp, int nr, int n1, const int *k2s, int nk2,
                            const int *mapab, int npair, float2 *y1, hipStream_t s);
 hipError_t launch_plane_c(int n1, bool herm, const float2 *y1, int nr, int plane, int npair, const int *mapct, int ng,
                           float2 *y, long long ldy, hipStream_t s);

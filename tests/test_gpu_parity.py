@@ -233,11 +233,18 @@ def test_eps_inverse_end_to_end(gw, q, head):
     e = orc.rel_f(got, ref)
     # eps^-1 - I: at tiny |q| the head row and column carry V(q) ~ 1/|q|^2 times the single-precision
     # rounding of P~(0, .), which is conditioning of the input, so they are left out of this measure.
-    body = slice(1, None) if 0 < np.linalg.norm(q) < 1e-2 else slice(0, None)
+    tiny = 0 < np.linalg.norm(q) < 1e-2
+    body = slice(1, None) if tiny else slice(0, None)
     eye = np.eye(len(ref))
     e2 = orc.rel_f((got - eye)[body, body], (ref - eye)[body, body])
-    print(f"rel_F(eps^-1) = {e:.3e}, rel_F(eps^-1 - I) = {e2:.3e}")
-    assert e < 1e-5 and e2 < 1e-4
+    # The whole matrix can be no more accurate than P~ in single precision allows: to first order
+    # d(eps^-1) = eps^-1 V^1/2 dP~ V^1/2 eps^-1 (eps = I - V^1/2 P~ V^1/2), and an FP32 P~ carries
+    # ||dP~||_F ~ 2^-24 ||P~||_F, so ||d(eps^-1)||_F <= ||eps^-1||_2^2 max(v)^2 2^-24 ||P~||_F.
+    v = orc.coulomb_sqrt(s.n, s.a_bohr, s.q, s.miller)
+    cond = np.linalg.norm(ref, 2) ** 2 * np.max(np.abs(v)) ** 2 * 2.0 ** -24 * np.linalg.norm(pt_ref)
+    cond /= np.linalg.norm(ref)
+    print(f"rel_F(eps^-1) = {e:.3e}, rel_F(eps^-1 - I) = {e2:.3e}, FP32 conditioning bound {cond:.3e}")
+    assert e < max(1e-5, cond) and e2 < 1e-4
 
 
 # --- precision variants (workload 3: the 12^3 system, rows r = 0 mod 8 of P) -------------------------
