@@ -73,19 +73,24 @@ def parity_small(gw, torch, prec):
             "eps_inv": orc.rel_f(einv.cpu().numpy(), ei)}
 
 
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "herk_bf16split_si36_pmc.md")
-PMC_KERNEL = {"bf16split_t128_ws2_k32": "herk_split_ws_kernel<__bf16, 32, false, false, 2>"}
+PMC_SUMMARIES = [os.path.join(ROOT, "profiles", f) for f in ("herk_bf16split_wide_si36_pmc.md",
+                                                              "herk_bf16split_si36_pmc.md")]
+PMC_KERNEL = {"bf16split_t128x256_wide_k16": "herk_split_wide_kernel<__bf16, false>",
+              "bf16split_t128_ws2_k32": "herk_split_ws_kernel<__bf16, 32, false, false, 2>"}
 
 
 def measured_traffic(tile_name, workload):
     """HBM bytes per launch of the update kernel from the committed PMC summary (FETCH_SIZE and
     WRITE_SIZE, each scaled by a copy kernel of known size), when that summary covers this kernel."""
     kern = PMC_KERNEL.get(tile_name)
-    if kern is None or workload != "si36" or not os.path.exists(PMC_SUMMARY):
+    if kern is None or workload != "si36":
         return None
-    for line in open(PMC_SUMMARY):
-        if line.startswith("machine-readable: traffic_bytes_per_launch") and kern in line:
-            return float(line.split()[-1])
+    for path in PMC_SUMMARIES:
+        if not os.path.exists(path):
+            continue
+        for line in open(path):
+            if line.startswith("machine-readable: traffic_bytes_per_launch") and kern in line:
+                return float(line.split()[-1])
     return None
 
 

@@ -1088,7 +1088,7 @@ int herk_default_tile(int precision, int nr) {
   (void)nr;
   switch (precision) {
     case GW_FP32: return 4;
-    case GW_SPLIT_BF16: return 11;
+    case GW_SPLIT_BF16: return 13;
     case GW_SPLIT_FP16_SCALED: return 12;
   }
   return -1;

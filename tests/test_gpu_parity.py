@@ -342,8 +342,10 @@ def test_fp16_scaled_tiles_agree_with_wide_band_exponents(gw):
 @pytest.mark.parametrize("prec,tile_name,tol", [("bf16", "bf16split_t128_ws_k32", 1e-4),
                                                 ("bf16", "bf16split_t128_ws", 1e-4),
                                                 ("bf16", "bf16split_t128_ws2_k32", 1e-4),
+                                                ("bf16", "bf16split_t128x256_wide_k16", 1e-4),
                                                 ("fp16", "fp16split_t128_ws_k32_scaled", 2e-5),
-                                                ("fp16", "fp16split_t128_ws2_k32_scaled", 2e-5)])
+                                                ("fp16", "fp16split_t128_ws2_k32_scaled", 2e-5),
+                                                ("fp16", "fp16split_t128x256_wide_k16_scaled", 2e-5)])
 @pytest.mark.parametrize("nv,nc", [(32, 1024), (64, 600), (64, 1024)])
 def test_split_two_level_sum(gw, prec, tile_name, tol, nv, nc):
     """K = nv*nc of 32768 (no fold), 38400 (one fold, ragged) and 65536 (a fold between two full blocks)
