@@ -10,6 +10,8 @@
 //   Re C += [Re A, Im A] . [Re B; -Im B],   Im C += [Re A, Im A] . [Im B; Re B].
 #include <algorithm>
 
+#include <utility>
+
 #include "gw_internal.h"
 
 namespace gwi {
@@ -227,6 +229,22 @@ hipError_t launch_zgemm(int M, int N, int K, const double2 *A, long long lda, in
 // panel L[k0+nb+64g : +64, k0 : k0+nb] = A Linv_kk^H.
 constexpr int NB = 32;
 
+// 1 / d for a positive finite d: the hardware estimate refined by two Newton steps r <- r + r (1 - d r),
+// each of which squares the relative error (within an ulp or two of the rounded quotient); three
+// dependent operations fewer than the correctly rounded division on the factorisation's latency chain
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
+
+// f(integral_constant<int, J>) for J = 0, 1, ...: loop bodies whose index must be a constant
+template <typename F, int... J>
+__device__ __forceinline__ void static_for(F &&f, std::integer_sequence<int, J...>) {
+  (f(std::integral_constant<int, J>{}), ...);
+}
+
 __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restrict__ A, int n, int k0,
                                                          double2 *__restrict__ L, double2 *__restrict__ linv,
                                                          int *__restrict__ pivot) {
@@ -256,53 +274,71 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
     x[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   // Unblocked right-looking Cholesky on the lower triangle, with unscaled columns: step j subtracts
-  // s_j s_j^H / d_j (d_j the pivot, s_j column j) from the trailing lower triangle, one barrier per step.
-  // In elimination form A = Lu D Lu^H with Lu = I + sum_j (s_j / d_j) e_j^T below the diagonal, so the
-  // same step also applies Lu's j-th elimination to X (started as I): row i > j loses (s_j(i) / d_j)
-  // times row j, on the columns m <= j where row j is non-zero.  After the last step X = Lu^-1, and
-  // L = Lu D^1/2, L^-1 = D^-1/2 X follow by scaling.  A thread owns column m = tid % NB of rows
-  // tid / NB + 8t: for each row the factor update (m > j) and the X update (m <= j) are disjoint, and
-  // neither writes column j of a or row j of X, so every read of the step is issued before its writes.
+  // s_j s_j^H / d_j (d_j the pivot, s_j column j) from the trailing lower triangle.  In elimination form
+  // A = Lu D Lu^H with Lu = I + sum_j (s_j / d_j) e_j^T below the diagonal, so the same step also applies
+  // Lu's j-th elimination to X (started as I): row i > j loses (s_j(i) / d_j) times row j, on the columns
+  // m <= j where row j is non-zero.  After the last step X = Lu^-1, and L = Lu D^1/2, L^-1 = D^-1/2 X
+  // follow by scaling.
+  //
+  // The 32 steps form the kernel's latency chain.  The block lives in registers, spread over all four
+  // waves: lane (m, c) = (tid % 32, tid / 32) keeps one column on the rows i = 8t + c, so each lane
+  // updates four rows per step.  Column m of A changes only in the steps j < m and column m of X only in
+  // the steps j >= m (X is I on it until then), so the lanes of column m hold A's column until step m,
+  // where they pass it on and take X's identity column in its place.  Step j's column of the factor and
+  // row of X go to LDS rows of their own (colj[j], xrowj[j]), so one barrier per step orders the writes
+  // before the reads and no step overwrites what another still reads.  Every lane then subtracts
+  // s_j(i) w on its rows i > j, with w = conj(s_j(m)) / d_j while it holds A (m > j) and X[j][m] / d_j
+  // once it holds X.  On A's columns this also writes rows j < i < m above the diagonal; those rows are
+  // never read, and X's column is zeroed above its diagonal when it is stored.
+  __shared__ double2 colj[NB][NB + 1], xrowj[NB][NB + 1];
   {
-    const int m = tid % NB, ib = tid / NB;
-    for (int j = 0; j < NB; ++j) {
+    constexpr int C = 8, T = NB / C;                        // row classes, rows per lane
+    const int m = tid % NB, c = tid / NB;
+    double2 z[T];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < T; ++t) z[t] = a[C * t + c][m];
+    int badj = 0;
+    auto step = [&](auto jc) {                                 // step j, a compile-time index
+      constexpr int j = decltype(jc)::value, jt = j / C, jr = j % C;
+      if (m == j) {
+#pragma unroll
+        for (int t = jt; t < T; ++t) colj[j][C * t + c] = z[t];     // column j, final from here on
+#pragma unroll
+        for (int t = jt; t < T; ++t) z[t] = make_double2(C * t + c == m ? 1.0 : 0.0, 0.0);   // X's column
+      }
+      if (c == jr) xrowj[j][m] = z[jt];                        // row j of X (read only where m <= j)
       __syncthreads();
-      double d = a[j][j].x;
-      if (!(d > 0.0) || !isfinite(d)) {
-        if (tid == 0 && j < nb && bad == 0) bad = k0 + j + 1;
-        d = 1.0;
-      }
-      const double dinv = 1.0 / d;
-      const double2 q = a[m][j], xq = x[j][m];
-      double2 p[NB * NB / 256], c[NB * NB / 256], xc[NB * NB / 256];
+      const double d0 = colj[j][j].x;
+      const double2 q = colj[j][m], xq = xrowj[j][m];
+      double2 pj[T];
 #pragma unroll
-      for (int t = 0; t < NB * NB / 256; ++t) {
-        p[t] = a[ib + 8 * t][j];
-        c[t] = a[ib + 8 * t][m];
-        xc[t] = x[ib + 8 * t][m];
-      }
+      for (int t = jt; t < T; ++t) pj[t] = colj[j][C * t + c];
+      const bool okd = d0 > 0.0 && isfinite(d0);
+      badj = (!okd && j < nb && badj == 0) ? k0 + j + 1 : badj;
+      const double dinv = recip(okd ? d0 : 1.0);
+      const bool fac = m > j;
+      const double wx = (fac ? q.x : xq.x) * dinv;
+      const double wy = (fac ? -q.y : xq.y) * dinv;
 #pragma unroll
-      for (int t = 0; t < NB * NB / 256; ++t) {
-        const int i = ib + 8 * t;
-        if (m > j && m <= i) {
-          c[t].x -= (p[t].x * q.x + p[t].y * q.y) * dinv;
-          c[t].y -= (p[t].y * q.x - p[t].x * q.y) * dinv;
-          a[i][m] = c[t];
-        } else if (m <= j && i > j) {
-          const double lr = p[t].x * dinv, li = p[t].y * dinv;
-          xc[t].x -= lr * xq.x - li * xq.y;
-          xc[t].y -= lr * xq.y + li * xq.x;
-          x[i][m] = xc[t];
+      for (int t = jt; t < T; ++t) {
+        if (t > jt || c > jr) {                                // rows i > j
+          z[t].x -= pj[t].x * wx - pj[t].y * wy;
+          z[t].y -= pj[t].x * wy + pj[t].y * wx;
         }
       }
-    }
+    };
+    static_for(step, std::make_integer_sequence<int, NB>{});
+#pragma unroll
+    for (int t = 0; t < T; ++t) x[C * t + c][m] = C * t + c >= m ? z[t] : make_double2(0.0, 0.0);
+    if (tid == 0) bad = badj;
   }
   __syncthreads();
   // r_j = sqrt(d_j) (bad pivots were replaced by 1 and flagged); L = column j over r_j, L^-1 = row i of X
   // over r_i
   __shared__ double rs[NB];
   if (tid < NB) {
-    double d = a[tid][tid].x;
+    double d = colj[tid][tid].x;
     if (!(d > 0.0) || !isfinite(d)) d = 1.0;
     rs[tid] = sqrt(d);
   }
@@ -311,7 +347,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
     const int i = idx / NB, j = idx % NB;
     if (j <= i) {
       const double r = rs[j];
-      a[i][j] = (i == j) ? make_double2(r, 0.0) : make_double2(a[i][j].x / r, a[i][j].y / r);
+      a[i][j] = (i == j) ? make_double2(r, 0.0) : make_double2(colj[j][i].x / r, colj[j][i].y / r);
     }
     const double ri = rs[i];
     x[i][j] = make_double2(x[i][j].x / ri, x[i][j].y / ri);
@@ -504,32 +540,18 @@ size_t chol_small_bytes(int n) {
 #define GW_TRY(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
 
 hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small, int *pivot_dev, double2 *out,
-                       hipStream_t s, hipStream_t side, hipEvent_t ev_fork, hipEvent_t ev_side) {
+                       hipStream_t s) {
   const size_t nn = (size_t)n * n;
   const unsigned fill_blocks = (unsigned)((nn + 255) / 256);
-  // Look-ahead (when a second stream is given): after each panel, this stream applies the panel's
-  // update only to the next panel's columns (or rows) and goes on with the latency-bound chain of the
-  // next panel, while `side` applies it to everything beyond.  Before its next look-ahead product this
-  // stream waits for the side product, which writes the region that product reads and writes.
-  const bool la = side != nullptr && ev_fork != nullptr && ev_side != nullptr;
-  bool pending = false;                          // a side product is in flight
-  auto join = [&]() -> hipError_t {
-    if (!pending) return hipSuccess;
-    pending = false;
-    return hipStreamWaitEvent(s, ev_side, 0);
-  };
-  auto fork = [&]() -> hipError_t {
-    GW_TRY(hipEventRecord(ev_fork, s));
-    GW_TRY(hipStreamWaitEvent(side, ev_fork, 0));
-    pending = true;
-    return hipSuccess;
-  };
   GW_TRY(launch_fill_int(pivot_dev, 0, s));
   hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, l, n, 0.0);
   GW_TRY(hipGetLastError());
   // Panels of PW columns: inside a panel each NB-wide step updates only the panel's columns; one
   // K = PW product then updates everything right of (factorisation) or below (substitution) the panel,
   // so the large trailing matrix is read and written once per panel instead of once per NB step.
+  // (A look-ahead that moved each panel's trailing product to a second stream, so that the next panel's
+  // chain could start at once, measured slower at N = 4067: the product's workgroups fill the CUs the
+  // chain's small launches wait for.)
   constexpr int PW = CHOL_PW;   // 128, 256 and 512 measured alike; 32 (no panels) 5% slower at N = 4067
   // 1. factor a = L L^H
   for (int p0 = 0; p0 < n; p0 += PW) {
@@ -554,25 +576,9 @@ hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small
     const int rest = n - p1;
     if (rest > 0) {
       const double2 *lp = l + (size_t)p1 * n + p0;
-      if (!la) {
-        GW_TRY(zgemm(rest, rest, p1 - p0, lp, n, 0, lp, n, 1, a + (size_t)p1 * n + p1, n, -1.0, 1.0, 1, 0, s));
-      } else {
-        const int p2 = min(n, p1 + PW);
-        GW_TRY(join());
-        // the next panel's columns here: A[p1:, p1:p2] (lower part)
-        GW_TRY(zgemm(rest, p2 - p1, p1 - p0, lp, n, 0, lp, n, 1, a + (size_t)p1 * n + p1, n, -1.0, 1.0, 1, 0, s));
-        if (p2 < n) {
-          // everything beyond on the side stream: A[p2:, p2:]
-          const double2 *lq = l + (size_t)p2 * n + p0;
-          GW_TRY(fork());
-          GW_TRY(zgemm(n - p2, n - p2, p1 - p0, lq, n, 0, lq, n, 1, a + (size_t)p2 * n + p2, n, -1.0, 1.0, 1, 0,
-                       side));
-          GW_TRY(hipEventRecord(ev_side, side));
-        }
-      }
+      GW_TRY(zgemm(rest, rest, p1 - p0, lp, n, 0, lp, n, 1, a + (size_t)p1 * n + p1, n, -1.0, 1.0, 1, 0, s));
     }
   }
-  GW_TRY(join());
   // 2. X = L^-1 by right-looking block substitution on B = I (B reuses a)
   hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, a, n, 1.0);
   GW_TRY(hipGetLastError());
@@ -586,27 +592,10 @@ hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small
     GW_TRY(hipGetLastError());
     // below the panel: B[p1:, :p1] -= L[p1:, p0:p1] X[p0:p1, :p1]
     const int rest = n - p1;
-    if (rest > 0) {
-      if (!la) {
-        GW_TRY(zgemm(rest, p1, p1 - p0, l + (size_t)p1 * n + p0, n, 0, x + (size_t)p0 * n, n, 0, a + (size_t)p1 * n,
-                     n, -1.0, 1.0, 0, 0, s));
-      } else {
-        const int p2 = min(n, p1 + PW);
-        GW_TRY(join());
-        // the next panel's rows here: B[p1:p2, :p1]
-        GW_TRY(zgemm(p2 - p1, p1, p1 - p0, l + (size_t)p1 * n + p0, n, 0, x + (size_t)p0 * n, n, 0,
-                     a + (size_t)p1 * n, n, -1.0, 1.0, 0, 0, s));
-        if (p2 < n) {
-          // the rows beyond on the side stream: B[p2:, :p1]
-          GW_TRY(fork());
-          GW_TRY(zgemm(n - p2, p1, p1 - p0, l + (size_t)p2 * n + p0, n, 0, x + (size_t)p0 * n, n, 0,
-                       a + (size_t)p2 * n, n, -1.0, 1.0, 0, 0, side));
-          GW_TRY(hipEventRecord(ev_side, side));
-        }
-      }
-    }
+    if (rest > 0)
+      GW_TRY(zgemm(rest, p1, p1 - p0, l + (size_t)p1 * n + p0, n, 0, x + (size_t)p0 * n, n, 0, a + (size_t)p1 * n, n,
+                   -1.0, 1.0, 0, 0, s));
   }
-  GW_TRY(join());
   // 3. out = X^H X (lower tiles, k from max(row, col) since X is lower triangular), then mirror
   GW_TRY(zgemm(n, n, n, x, n, 1, x, n, 0, out, n, 1.0, 0.0, 1, 1, s));
   dim3 mg((n + 31) / 32, (n + 31) / 32);

@@ -436,12 +436,7 @@ int hpd_inverse_impl(gw_ctx *ctx, double2 *a, int n, double2 *out, hipStream_t s
   GW_STATUS(ws_get(ctx, WS_CHOL_X, (size_t)n * n * sizeof(double2), &x, s));
   GW_STATUS(ws_get(ctx, WS_CHOL_SMALL, chol_small_bytes(n) + 256, &sm, s));
   piv = (char *)sm + chol_small_bytes(n);
-  if (!ctx->chol_side) {
-    GW_HIP(ctx, hipStreamCreateWithFlags(&ctx->chol_side, hipStreamNonBlocking));
-    for (hipEvent_t &e : ctx->chol_ev) GW_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  }
-  GW_HIP(ctx, hpd_inverse(a, n, (double2 *)l, (double2 *)x, (double2 *)sm, (int *)piv, out, s, ctx->chol_side,
-                          ctx->chol_ev[0], ctx->chol_ev[1]));
+  GW_HIP(ctx, hpd_inverse(a, n, (double2 *)l, (double2 *)x, (double2 *)sm, (int *)piv, out, s));
   GW_HIP(ctx, hipMemcpyAsync(ctx->pivot_host, piv, sizeof(int), hipMemcpyDeviceToHost, s));
   GW_HIP(ctx, hipStreamSynchronize(s));
   if (*ctx->pivot_host != 0) {
@@ -521,9 +516,6 @@ int gw_destroy(gw_ctx *ctx) {
     if (hipSetDevice(ctx->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) st = GW_E_HIP;
     gwi::batched_release(ctx);
     gwi::tail_graphs_release(ctx);
-    for (hipEvent_t e : ctx->chol_ev)
-      if (e) (void)hipEventDestroy(e);
-    if (ctx->chol_side) (void)hipStreamDestroy(ctx->chol_side);
     for (auto &sl : ctx->slots)
       if (sl.ptr) (void)hipFree(sl.ptr);
     if (ctx->pivot_host) (void)hipHostFree(ctx->pivot_host);

@@ -375,9 +375,6 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
       if (jb.eps_inv) {
         ck(launch_sqrtv(jd[j].miller, ng, jb.q[0], jb.q[1], jb.q[2], grid.a_bohr, jd[j].sqrtv, c->sb));
         ck(launch_eps_build((const float2 *)jb.p_gg, ng, jd[j].sqrtv, head, (double2 *)weps, c->sb));
-        // no look-ahead inside the captured graph: the 32^3 eight-q batch with per-panel fork/join events
-        // ended the process during capture, with no cause found in this code; the graph already overlaps
-        // this factorisation with the next job's update
         ck(hpd_inverse((double2 *)weps, ng, (double2 *)wl, (double2 *)wx, (double2 *)wsmall,
                        (int *)((char *)wpiv + 64 * j), (double2 *)jb.eps_inv, c->sb));
       }

@@ -27,8 +27,6 @@ struct gw_ctx {
   int *pivot_host = nullptr;  // pinned host word for the Cholesky pivot flag
   void *graph_cache = nullptr;  // batched-q graphs (owned; see gw_batched.cpp)
   void *tail_graphs = nullptr;  // training-step graphs of the learned tail (owned; see gw_tail.cpp)
-  hipStream_t chol_side = nullptr;           // second stream of the Cholesky look-ahead (default priority)
-  hipEvent_t chol_ev[2] = {nullptr, nullptr};
   std::map<std::string, int> tuned;   // autotuned update tiles, keyed by arch and shape
   bool tune_loaded = false;           // the autotune cache file has been read
   std::string arch;                   // device architecture name (cached)
@@ -110,12 +108,8 @@ hipError_t launch_eps_build(const float2 *p_gg, int ng, const double *sv, double
 // Cholesky-based inverse of a Hermitian PD matrix (lower triangle of a read).  a is overwritten.
 // l, x: n*n workspaces; small: workspace of at least chol_small_bytes(n); pivot_dev: device int.
 size_t chol_small_bytes(int n);
-// side, ev_fork, ev_side (all or none): a second stream and two events for the look-ahead, which moves
-// each panel's large trailing product off the chain of the next panel; the call returns with `side`
-// joined into `s`.
 hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small, int *pivot_dev, double2 *out,
-                       hipStream_t s, hipStream_t side = nullptr, hipEvent_t ev_fork = nullptr,
-                       hipEvent_t ev_side = nullptr);
+                       hipStream_t s);
 hipError_t launch_fill_int(int *p, int value, hipStream_t s);
 // C = alpha op(A) op(B) + beta C, complex128, op = identity (0) or conjugate transpose (1); row-major.
 hipError_t launch_zgemm(int M, int N, int K, const double2 *A, long long lda, int transA, const double2 *B,
