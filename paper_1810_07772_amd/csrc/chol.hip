@@ -225,9 +225,11 @@ hipError_t launch_zgemm(int M, int N, int K, const double2 *A, long long lda, in
 
 // ---- diagonal block L_kk = chol(A_kk), Linv_kk = L_kk^-1, and the panel column below it -------------
 // Every workgroup factors and inverts the 32 x 32 block in LDS (cheap, and it saves a dependent launch
-// per step); workgroup 0 stores L_kk, Linv_kk and the pivot flag, and workgroup g forms 64 rows of the
-// panel L[k0+nb+64g : +64, k0 : k0+nb] = A Linv_kk^H.
+// per step); workgroup 0 stores L_kk, Linv_kk and the pivot flag, and workgroup g forms PR rows of the
+// panel L[k0+nb+PR g : +PR, k0 : k0+nb] = A Linv_kk^H.  With PR = 16 the panel product of a 4067-row
+// matrix spreads over about 250 CUs (64 rows per workgroup left three quarters of the CUs idle).
 constexpr int NB = 32;
+constexpr int PR = 16;    // panel rows per workgroup of the diagonal-block kernel
 
 // 1 / d for a positive finite d: the hardware estimate refined by two Newton steps r <- r + r (1 - d r),
 // each of which squares the relative error (within an ulp or two of the rounded quotient); three
@@ -250,17 +252,17 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
                                                          int *__restrict__ pivot) {
   __shared__ double2 a[NB][NB + 1];
   __shared__ double2 x[NB][NB + 1];
-  __shared__ double2 pa[64][NB + 1];
+  __shared__ double2 pa[PR][NB + 1];
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int nb = min(NB, n - k0);
-  // this workgroup's 64 panel rows below the block, loaded now so that their latency overlaps the
+  // this workgroup's PR panel rows below the block, loaded now so that their latency overlaps the
   // factorisation: thread (pib, pj) holds A[r0 + pib + 8t][k0 + pj]
-  const int r0 = k0 + nb + (int)blockIdx.x * 64;
+  const int r0 = k0 + nb + (int)blockIdx.x * PR;
   const int pj = tid % NB, pib = tid / NB;
-  double2 pv[64 * NB / 256];
+  double2 pv[PR * NB / 256];
 #pragma unroll
-  for (int t = 0; t < 64 * NB / 256; ++t) {
+  for (int t = 0; t < PR * NB / 256; ++t) {
     const int r = r0 + pib + 8 * t;
     pv[t] = (r < n && pj < nb) ? A[(size_t)r * n + k0 + pj] : make_double2(0.0, 0.0);
   }
@@ -361,29 +363,29 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
     }
     if (tid == 0 && bad != 0 && *pivot == 0) *pivot = bad;
   }
-  // panel below the block, 64 rows per workgroup (every workgroup factored the block above for itself):
+  // panel below the block, PR rows per workgroup (every workgroup factored the block above for itself):
   // L[r][k0 + j] = sum_{k <= j} A[r][k0 + k] conj(Linv[j][k]).  Linv is lower triangular with its upper
-  // part stored as zeros, so the k loop runs to NB for every thread: no divergence, and eight
+  // part stored as zeros, so the k loop runs to NB for every thread: no divergence, and PR / 8
   // independent accumulators per thread (rows pib + 8t of column pj).
   if (r0 >= n) return;
 #pragma unroll
-  for (int t = 0; t < 64 * NB / 256; ++t) pa[pib + 8 * t][pj] = pv[t];
+  for (int t = 0; t < PR * NB / 256; ++t) pa[pib + 8 * t][pj] = pv[t];
   __syncthreads();
-  double2 acc[64 * NB / 256];
+  double2 acc[PR * NB / 256];
 #pragma unroll
-  for (int t = 0; t < 64 * NB / 256; ++t) acc[t] = make_double2(0.0, 0.0);
+  for (int t = 0; t < PR * NB / 256; ++t) acc[t] = make_double2(0.0, 0.0);
 #pragma unroll 4
   for (int k = 0; k < NB; ++k) {
     const double2 v = x[pj][k];
 #pragma unroll
-    for (int t = 0; t < 64 * NB / 256; ++t) {
+    for (int t = 0; t < PR * NB / 256; ++t) {
       const double2 av = pa[pib + 8 * t][k];
       acc[t].x += av.x * v.x + av.y * v.y;
       acc[t].y += av.y * v.x - av.x * v.y;
     }
   }
 #pragma unroll
-  for (int t = 0; t < 64 * NB / 256; ++t) {
+  for (int t = 0; t < PR * NB / 256; ++t) {
     const int r = r0 + pib + 8 * t;
     if (r < n && pj < nb) L[(size_t)r * n + k0 + pj] = acc[t];
   }
@@ -428,7 +430,8 @@ hipError_t launch_fill_int(int *p, int value, hipStream_t s) {
 // 32-row steps in LDS: X_k = Linv_kk B_k, then B_i -= L_ik X_k for the panel's later row blocks.
 // One launch per panel replaces two small GEMMs per step.
 constexpr int CHOL_PW = 128;   // panel width of the factorisation and the substitution
-constexpr int SUB_CW = 32;     // columns per workgroup
+constexpr int SUB_CW = 8;      // columns per workgroup
+constexpr int SUB_RS = 256 / SUB_CW;   // row stride of a thread's rows in a 32-row block
 
 __global__ __launch_bounds__(256) void subst_panel_kernel(const double2 *__restrict__ B, const double2 *__restrict__ L,
                                                           const double2 *__restrict__ linv_all,
@@ -471,7 +474,7 @@ __global__ __launch_bounds__(256) void subst_panel_kernel(const double2 *__restr
     __syncthreads();
     if (k0 + NB < p1) fetch(k0, k0 + NB);
     // X_k = Linv_kk B_k.  Linv_kk is stored with zeros above its diagonal, so m runs over the whole
-    // block for every thread: thread (i = ib + 8t, c) keeps PER independent sums.
+    // block for every thread: thread (i = ib + SUB_RS t, c) keeps PER independent sums.
     const int ib = tid / SUB_CW, c = tid % SUB_CW;
     double2 xv[PER];
 #pragma unroll
@@ -481,7 +484,7 @@ __global__ __launch_bounds__(256) void subst_panel_kernel(const double2 *__restr
       const double2 v = sB[kr + m][c];
 #pragma unroll
       for (int t = 0; t < PER; ++t) {
-        const double2 u = sM[ib + 8 * t][m];
+        const double2 u = sM[ib + SUB_RS * t][m];
         xv[t].x += u.x * v.x - u.y * v.y;
         xv[t].y += u.x * v.y + u.y * v.x;
       }
@@ -514,14 +517,14 @@ __global__ __launch_bounds__(256) void subst_panel_kernel(const double2 *__restr
         const double2 v = sB[kr + m][c];
 #pragma unroll
         for (int t = 0; t < PER; ++t) {
-          const double2 u = sM[ib + 8 * t][m];
+          const double2 u = sM[ib + SUB_RS * t][m];
           acc[t].x += u.x * v.x - u.y * v.y;
           acc[t].y += u.x * v.y + u.y * v.x;
         }
       }
 #pragma unroll
       for (int t = 0; t < PER; ++t) {
-        const int i = ib + 8 * t;
+        const int i = ib + SUB_RS * t;
         if (i < jn) {
           sB[jr + i][c].x -= acc[t].x;
           sB[jr + i][c].y -= acc[t].y;
@@ -560,7 +563,7 @@ hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small
       const int kb = k0 / NB, nb = min(NB, n - k0), rest = n - k0 - nb;
       double2 *linv = small + (size_t)kb * NB * NB;
       // the diagonal block and, in the same launch, the panel column L[k0+nb:, k0:k0+nb] = A Linv^H
-      hipLaunchKernelGGL(potrf_diag_kernel, dim3(std::max(1, (rest + 63) / 64)), dim3(256), 0, s, a, n, k0, l, linv,
+      hipLaunchKernelGGL(potrf_diag_kernel, dim3(std::max(1, (rest + PR - 1) / PR)), dim3(256), 0, s, a, n, k0, l, linv,
                          pivot_dev);
       GW_TRY(hipGetLastError());
       if (rest > 0) {
