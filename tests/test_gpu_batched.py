@@ -171,10 +171,10 @@ def test_batched_multi_panel_cholesky(gw):
         assert e1 < 1e-5 and e2 < 1e-5
 
 
-@pytest.mark.skip(reason="the process ended with a segmentation fault inside this call (32^3 batch, capture of the "
-                         "Cholesky look-ahead's per-panel fork/join events) and no cause was found in the library; "
-                         "the look-ahead is switched off inside the captured graph, and this case stays off the "
-                         "GPU until a cause is shown")
+@pytest.mark.skip(reason="the process once ended with a segmentation fault inside this call (32^3 batch, capture "
+                         "of the Cholesky look-ahead's per-panel fork/join events) and no cause was found; the "
+                         "look-ahead has since been removed from the library, which is not a shown cause, so this "
+                         "case stays off the GPU until one is")
 def test_batched_full_size_eight_q(gw):
     """Eight q on the 32^3 grid (Nv 96, Nc 768 each, spheres of 2500 .. 4500 G), split BF16, one graph.
     Checked on sampled outputs: P~ entries against the direct-sum Adler-Wiser oracle for two jobs, and
