@@ -773,7 +773,7 @@ __global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_kernel(const floa
       gpt[j] = min(pt < HB ? I0 + pt : J0 + (pt - HB), nr - 1);
     }
     float2 pc[3][8], pcn[3][8], pvv[3];
-    float sc[2][8];
+    float sc[3][8];                                        // the scale row of each unit's half
     auto load_c = [&](float2 (&dst)[3][8], int cc) {
 #pragma unroll
       for (int j = 0; j < 3; ++j)
@@ -792,17 +792,19 @@ __global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_kernel(const floa
         for (int j = 0; j < 3; ++j) { pvv[j].x *= m; pvv[j].y *= m; }
       }
       const float *srow = scale + (size_t)v * ldsc + c0;     // zero past nc: those pair products vanish
+      // per unit, at a wave-uniform offset, so that the multiplies take the scale straight from a scalar
+      // register (a select between the two halves' rows cost three VALU instructions per pair)
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int j = 0; j < 3; ++j)
 #pragma unroll
-        for (int k = 0; k < 8; ++k) sc[h][k] = srow[8 * h + k];
+        for (int k = 0; k < 8; ++k) sc[j][k] = srow[8 * half[j] + k];
     };
     auto produce = [&](int buf) {
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         u32x4 *dh = reinterpret_cast<u32x4 *>(&sH[buf][row[j]][16 * half[j]]);
         u32x4 *dl = reinterpret_cast<u32x4 *>(&sL[buf][row[j]][16 * half[j]]);
-        const float *s8 = half[j] ? sc[1] : sc[0];
+        const float *s8 = sc[j];
 #pragma unroll
         for (int g = 0; g < 2; ++g) {
           u32x4 hv, lv;
