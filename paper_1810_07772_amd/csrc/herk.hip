@@ -781,8 +781,7 @@ __global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_kernel(const floa
         for (int k = 0; k < 8; ++k)
           dst[j][k] = psi_c[(size_t)min(cc * WK + 8 * half[j] + k, nc - 1) * nr + gpt[j]];
     };
-    auto load_v = [&](int ch) {
-      const int vi = ch % nv, c0 = (ch / nv) * WK;
+    auto load_v = [&](int vi, int c0) {                    // psi_v and the scales of stage (vi, c0)
       const int v = SCALED ? order[vi] : vi;
 #pragma unroll
       for (int j = 0; j < 3; ++j) pvv[j] = psi_v[(size_t)v * nr + gpt[j]];
@@ -823,15 +822,19 @@ __global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_kernel(const floa
         }
       }
     };
+    // stage ch is (occupied band ch % nv, unoccupied chunk ch / nv); the stage indices ahead of the loop
+    // advance by counters, not by a division per stage (a lone producer wave per SIMD issues close to
+    // its limit, so its scalar work counts too)
+    int v1 = 1 % nv, v2 = 2 % nv, c2 = 2 / nv;             // stages ch + 1 and ch + 2
     load_c(pc, 0);
-    load_v(0);
+    load_v(0, 0);
     produce(0);
-    if (nch > 1) load_v(1);
+    if (nch > 1) load_v(v1, (1 / nv) * WK);
     if (nv == 1 && nch > 1) load_c(pcn, 1);
     __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {
       if (ch + 1 < nch) {
-        if ((ch + 1) % nv == 0) {                          // stage ch+1 opens the next unoccupied chunk
+        if (v1 == 0) {                                     // stage ch+1 opens the next unoccupied chunk
 #pragma unroll
           for (int j = 0; j < 3; ++j)
 #pragma unroll
@@ -839,10 +842,12 @@ __global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_kernel(const floa
         }
         produce((ch & 1) ^ 1);
         if (ch + 2 < nch) {
-          load_v(ch + 2);
-          if ((ch + 2) % nv == 0) load_c(pcn, (ch + 2) / nv);
+          load_v(v2, c2 * WK);
+          if (v2 == 0) load_c(pcn, c2);
         }
       }
+      v1 = v1 + 1 == nv ? 0 : v1 + 1;
+      if (++v2 == nv) { v2 = 0; ++c2; }
       __syncthreads();
     }
     return;
@@ -1091,7 +1096,7 @@ int herk_default_tile(int precision, int nr) {
   switch (precision) {
     case GW_FP32: return 4;
     case GW_SPLIT_BF16: return 13;
-    case GW_SPLIT_FP16_SCALED: return 12;
+    case GW_SPLIT_FP16_SCALED: return 14;
   }
   return -1;
 }
