@@ -128,6 +128,12 @@ def test_sphere_transform_long_axes(gw, n, r2, q):
 # only the upper triangle of P, are checked against the dense oracle, at q = 0 with a pruned sphere and at
 # q != 0 with every non-Nyquist vector.
 PLANE_GRIDS = [(5, 24, 24), (6, 32, 32), (4, 36, 36), (12, 12, 12), (9, 8, 8), (10, 5, 5)]
+# every other supported length: as n2 = n3 (the in-plane kernel, its planes per wave chosen per length and
+# sphere) and as n1 (the i1 kernel); (5, 48, 48) with the whole grid's sphere has 8836 vectors, more than the
+# i1 kernel stages in LDS, so it also takes that kernel's direct-store path
+PLANE_GRIDS += [(5, 48, 48), (4, 40, 40), (4, 30, 30), (4, 27, 27), (4, 20, 20), (4, 18, 18), (4, 15, 15),
+                (4, 10, 10), (5, 4, 4), (48, 4, 4), (40, 4, 4), (36, 4, 4), (32, 4, 4), (30, 4, 4), (27, 4, 4),
+                (24, 4, 4), (20, 4, 4), (18, 4, 4), (16, 4, 4), (15, 4, 4), (8, 4, 4)]
 
 
 def hermitian_c64(nr, seed):
