@@ -631,6 +631,130 @@ hipError_t launch_plane_c(int n1, bool herm, const float2 *y1, int nr, int plane
   return hipGetLastError();
 }
 
+// ---- orbitals from plane-wave coefficients, row-contiguous (the sphere transform's plane path run in
+// reverse, band-major throughout) ------------------------------------------------------------------------
+// psi_b(r) = N_r^-1/2 sum_m c_bm exp(+i G_m.r) in two steps.  orb_c: thread (band b, pair p) gathers the
+// pair's k1 column from the band's coefficients (mapct, -1 off the sphere), scaled, and transforms it over
+// k1: y[b][i1][p].  orb_plane: one wave per band and pl consecutive i1 planes stages those planes' pair
+// values in LDS, transforms each row k2 that carries pairs over k3 (one lane per row), then every column i3
+// over k2 (one lane per column, zero where k2 has no pair), and stores the planes of psi_b contiguously.
+template <int N1>
+__global__ __launch_bounds__(256) void orb_c_kernel(const float2 *__restrict__ coeff, int npw, int nb,
+                                                    const int *__restrict__ mapct, int npair, float scale,
+                                                    float2 *__restrict__ y) {
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long long)nb * npair) return;
+  const int b = (int)(idx / npair), p = (int)(idx - (long long)b * npair);
+  const float2 *cb = coeff + (size_t)b * npw;
+  float2 x[N1];
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) {
+    // every load unconditional (a valid index, scaled by zero off the sphere), so all are in flight at once
+    const int g = mapct[k1 * npair + p];
+    const float m = g >= 0 ? scale : 0.f;
+    const float2 v = cb[g >= 0 ? g : 0];
+    x[k1] = make_float2(v.x * m, v.y * m);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  Fft<N1, 1>::run(x);
+  float2 *yb = y + (size_t)b * N1 * npair + p;
+#pragma unroll
+  for (int i1 = 0; i1 < N1; ++i1) yb[(size_t)i1 * npair] = x[i1];
+}
+
+template <int N>
+__global__ __launch_bounds__(128) void orb_plane_kernel(const float2 *__restrict__ y, int n1, int pl,
+                                                        const int *__restrict__ k2s, int nk2,
+                                                        const int *__restrict__ mapab, int npair,
+                                                        float2 *__restrict__ psi, long long ldpsi) {
+  // two waves: wave 0 transforms the rows (pl nk2 <= 64), both transform the columns (pl n <= 128 at n = 36)
+  constexpr int PLN = N * N, LD = N + 1;
+  extern __shared__ float2 lds[];                 // [pl][npair] pair values, then [pl][nk2][LD] rows over them
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x, i10 = blockIdx.y * pl;
+  const int pend = min(pl, n1 - i10);
+  const float2 *src = y + ((size_t)b * n1 + i10) * npair;
+  for (int j = tid; j < pend * npair; j += 128) lds[j] = src[j];
+  __syncthreads();
+  {
+    const int p = tid / nk2, sl = tid - p * nk2;
+    const bool act = tid < 64 && p < pend;         // wave 0 alone: its reads are issued before its writes
+    float2 x[N];
+    if (act) {
+      const int *mrow = mapab + sl * N;
+      const float2 *yp = lds + p * npair;
+#pragma unroll
+      for (int k3 = 0; k3 < N; ++k3) {
+        const int pid = mrow[k3];
+        x[k3] = pid >= 0 ? yp[pid] : make_float2(0.f, 0.f);
+      }
+    }
+    __syncthreads();                               // every pair value read: the rows may overwrite them
+    if (act) {
+      Fft<N, 1>::run(x);
+      float2 *row = lds + (p * nk2 + sl) * LD;
+#pragma unroll
+      for (int i3 = 0; i3 < N; ++i3) row[i3] = x[i3];
+    }
+  }
+  __syncthreads();
+  for (int t0 = 0; t0 < pl * N; t0 += 128) {
+    const int t = t0 + tid, p = t / N, i3 = t - p * N;
+    if (p < pend) {
+      const float2 *col = lds + p * nk2 * LD + i3;
+      float2 x[N];
+#pragma unroll
+      for (int k2 = 0; k2 < N; ++k2) {
+        const int sl = k2s[k2];                        // uniform
+        x[k2] = sl >= 0 ? col[sl * LD] : make_float2(0.f, 0.f);
+      }
+      Fft<N, 1>::run(x);
+      float2 *dst = psi + (size_t)b * ldpsi + (size_t)(i10 + p) * PLN + i3;
+#pragma unroll
+      for (int i2 = 0; i2 < N; ++i2) dst[i2 * N] = x[i2];
+    }
+  }
+}
+
+hipError_t launch_orb_c(int n1, const float2 *coeff, int npw, int nb, const int *mapct, int npair, float scale,
+                        float2 *y, hipStream_t s) {
+  const long long nt = (long long)nb * npair;
+  if (nt <= 0) return hipSuccess;
+  if ((nt + 255) / 256 > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((nt + 255) / 256)), block(256);
+  switch (n1) {
+#define GW_CASE(n_)                                                                                                 \
+  case n_:                                                                                                          \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(orb_c_kernel<n_>), grid, block, 0, s, coeff, npw, nb, mapct, npair, scale, y); \
+    break;
+    GW_FFT_SIZES(GW_CASE)
+#undef GW_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_orb_plane(int n, const float2 *y, int nb, int n1, const int *k2s, int nk2, const int *mapab,
+                            int npair, float2 *psi, long long ldpsi, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  if (nk2 < 1 || nk2 > n || nk2 > 64 || npair > nk2 * n) return hipErrorInvalidValue;
+  const int pl = plane_ab_planes(n, nk2, n1);
+  const dim3 grid(nb, (n1 + pl - 1) / pl), block(128);
+  const size_t shm = (size_t)pl * std::max(npair, nk2 * (n + 1)) * sizeof(float2);
+  if (grid.y > 65535 || shm > 64 * 1024) return hipErrorInvalidValue;
+  switch (n) {
+#define GW_CASE(n_)                                                                                                  \
+  case n_:                                                                                                           \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(orb_plane_kernel<n_>), grid, block, shm, s, y, n1, pl, k2s, nk2, mapab, npair, \
+                       psi, ldpsi);                                                                                  \
+    break;
+    GW_FFT_SIZES(GW_CASE)
+#undef GW_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_add_adjoint(const float2 *x, int n, float2 *out, hipStream_t s) {
   dim3 grid((n + 31) / 32, (n + 31) / 32);
   if (grid.y > 65535) return hipErrorInvalidValue;

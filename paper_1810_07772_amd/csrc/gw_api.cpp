@@ -610,7 +610,25 @@ int gw_orbitals_to_grid(gw_ctx *ctx, const gw_c32 *coeff, int nb, int npw, gw_gr
   const int nr = (int)nrl;
   SpherePlan p;
   int *dA, *dB, *dC;
-  GW_STATUS(upload_plan(ctx, grid, pw_miller, npw, WS_ORB_MAP, p, &dA, &dB, &dC, s));
+  const int *extra[3] = {nullptr, nullptr, nullptr};   // k2 list + slot table, (k2, k3) pair slots, (k1, pair) map
+  GW_STATUS(upload_plan(ctx, grid, pw_miller, npw, WS_ORB_MAP, p, &dA, &dB, &dC, s, extra));
+  const float scale = (float)(1.0 / std::sqrt((double)nr));
+  const float2 *c = (const float2 *)coeff;
+  float2 *out = (float2 *)psi;
+  if (p.plane) {
+    // row-contiguous: y [w][n1][npair] per chunk of w bands (near 1 GiB), then the planes of each band
+    const size_t per_band = (size_t)p.n1 * p.npair;
+    const int w = (int)std::min<long long>(nb, std::max<long long>(1, (1LL << 27) / (long long)per_band));
+    void *y;
+    GW_STATUS(ws_get(ctx, WS_ORB_A1, per_band * w * sizeof(float2), &y, s));
+    for (int b0 = 0; b0 < nb; b0 += w) {
+      const int bw = std::min(w, nb - b0);
+      GW_HIP(ctx, launch_orb_c(p.n1, c + (size_t)b0 * npw, npw, bw, extra[2], p.npair, scale, (float2 *)y, s));
+      GW_HIP(ctx, launch_orb_plane(p.n3, (const float2 *)y, bw, p.n1, extra[0] + p.nk2, p.nk2, extra[1], p.npair,
+                                   out + (size_t)b0 * nr, nr, s));
+    }
+    return GW_OK;
+  }
   // band chunk: an intermediate of [nr][w] elements would stay near 1 GiB
   const int w = (int)std::min<long long>(nb, std::max<long long>(64, (1LL << 27) / nr));
   const size_t rows1 = (size_t)p.n1 * p.n2 * p.m3count, rows2 = (size_t)p.n1 * p.npair;
@@ -618,9 +636,6 @@ int gw_orbitals_to_grid(gw_ctx *ctx, const gw_c32 *coeff, int nb, int npw, gw_gr
   GW_STATUS(ws_get(ctx, WS_ORB_T, (size_t)npw * w * sizeof(float2), &ct, s));
   GW_STATUS(ws_get(ctx, WS_ORB_A1, rows1 * w * sizeof(float2), &a1, s));
   GW_STATUS(ws_get(ctx, WS_ORB_A2, rows2 * w * sizeof(float2), &a2, s));
-  const float scale = (float)(1.0 / std::sqrt((double)nr));
-  const float2 *c = (const float2 *)coeff;
-  float2 *out = (float2 *)psi;
   for (int b0 = 0; b0 < nb; b0 += w) {
     const int bw = std::min(w, nb - b0);
     float2 *t = (float2 *)ct, *x1 = (float2 *)a1, *x2 = (float2 *)a2;

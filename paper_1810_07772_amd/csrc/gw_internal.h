@@ -223,6 +223,12 @@ hipError_t launch_plane_ab(int n, bool herm, const float2 *p, long long ldp, int
                            const int *mapab, int npair, float2 *y1, hipStream_t s);
 hipError_t launch_plane_c(int n1, bool herm, const float2 *y1, int nr, int plane, int npair, const int *mapct, int ng,
                           float2 *y, long long ldy, hipStream_t s);
+// orbitals, row-contiguous (n2 == n3): y[b][i1][pair] = sum_k1 of the band's sphere coefficients over k1 (scaled), then
+// the planes of psi[b] (row stride ldpsi) from y
+hipError_t launch_orb_c(int n1, const float2 *coeff, int npw, int nb, const int *mapct, int npair, float scale,
+                        float2 *y, hipStream_t s);
+hipError_t launch_orb_plane(int n, const float2 *y, int nb, int n1, const int *k2s, int nk2, const int *mapab,
+                            int npair, float2 *psi, long long ldpsi, hipStream_t s);
 hipError_t launch_add_adjoint(const float2 *x, int n, float2 *out, hipStream_t s);
 // One 3-D transform over the row index of `in` ([nr][B], row stride ld_in) to the sphere rows of
 // `out` ([ng][B], row stride ld_out), in column chunks of at most bc (a1, a2 hold rowsA*bc and
