@@ -61,6 +61,53 @@ __global__ __launch_bounds__(PP_THREADS) void pair_products_kernel(const float2 
     two[h] = p + 1 < nr;
     wide[h] = two[h] && ((nr & 1) == 0);
   }
+  if ((nr & 1) == 0 && ((int)blockIdx.x + 1) * PP_CHUNK <= nr) {
+    // every point of the workgroup exists and pairs are 16-byte aligned: no per-lane condition anywhere,
+    // so the wait for the next band's prefetched psi_c counts past this band's stores instead of draining
+    // them (on this architecture one counter covers both)
+    for (int vb = 0; vb < nv; vb += PP_VB) {
+      const int nvb = min(PP_VB, nv - vb);
+      f32x4 vv[PP_NH][PP_VB];
+#pragma unroll
+      for (int h = 0; h < PP_NH; ++h)
+#pragma unroll
+        for (int k = 0; k < PP_VB; ++k)
+          vv[h][k] = *reinterpret_cast<const f32x4 *>(psi_v + (size_t)(vb + min(k, nvb - 1)) * nr + base + 128 * h);
+      f32x4 cv[PP_NH], cn[PP_NH];
+#pragma unroll
+      for (int h = 0; h < PP_NH; ++h) {
+        cv[h] = *reinterpret_cast<const f32x4 *>(psi_c + (size_t)min(cg0, nc - 1) * nr + base + 128 * h);
+        cn[h] = cv[h];
+      }
+      for (int cc = 0; cc < PP_CG; ++cc) {
+        const int c = cg0 + cc;
+        if (c >= nc) break;
+        if (cc + 1 < PP_CG && c + 1 < nc) {
+#pragma unroll
+          for (int h = 0; h < PP_NH; ++h)
+            cn[h] = *reinterpret_cast<const f32x4 *>(psi_c + (size_t)(c + 1) * nr + base + 128 * h);
+        }
+        float sk[PP_VB];
+#pragma unroll
+        for (int k = 0; k < PP_VB; ++k) sk[k] = scale[(vb + min(k, nvb - 1)) * ldsc + c];
+#pragma unroll
+        for (int k = 0; k < PP_VB; ++k) {
+          if (k < nvb) {                                     // uniform
+#pragma unroll
+            for (int h = 0; h < PP_NH; ++h) {
+              const float2 a = conj_mul_scale(make_float2(vv[h][k][0], vv[h][k][1]), make_float2(cv[h][0], cv[h][1]), sk[k]);
+              const float2 b = conj_mul_scale(make_float2(vv[h][k][2], vv[h][k][3]), make_float2(cv[h][2], cv[h][3]), sk[k]);
+              const f32x4 w = {a.x, a.y, b.x, b.y};
+              __builtin_nontemporal_store(w, reinterpret_cast<f32x4 *>(f + ((size_t)(vb + k) * nc + c) * nr + base + 128 * h));
+            }
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < PP_NH; ++h) cv[h] = cn[h];
+      }
+    }
+    return;
+  }
   for (int vb = 0; vb < nv; vb += PP_VB) {
     const int nvb = min(PP_VB, nv - vb);
     float2 v0[PP_NH][PP_VB], v1[PP_NH][PP_VB];
@@ -76,20 +123,29 @@ __global__ __launch_bounds__(PP_THREADS) void pair_products_kernel(const float2 
           if (two[h]) v1[h][k] = pv[1];
         }
       }
-    for (int cc = 0; cc < PP_CG; ++cc) {
-      const int c = cg0 + cc;
-      if (c >= nc) break;
-      float2 c0[PP_NH], c1[PP_NH];
+    // psi_c of the next unoccupied band is loaded while the current band's products are stored, so no
+    // band waits for its own loads; the band's PP_VB scales are read together before its stores
+    float2 c0[PP_NH], c1[PP_NH], n0[PP_NH] = {}, n1[PP_NH] = {};
+    auto load_c = [&](int c, float2 (&a)[PP_NH], float2 (&b)[PP_NH]) {
 #pragma unroll
       for (int h = 0; h < PP_NH; ++h) {
         const float2 *pc = psi_c + (size_t)c * nr + base + 128 * h;
-        c0[h] = one[h] ? pc[0] : make_float2(0.f, 0.f);
-        c1[h] = two[h] ? pc[1] : make_float2(0.f, 0.f);
+        a[h] = one[h] ? pc[0] : make_float2(0.f, 0.f);
+        b[h] = two[h] ? pc[1] : make_float2(0.f, 0.f);
       }
+    };
+    if (cg0 < nc) load_c(cg0, c0, c1);
+    for (int cc = 0; cc < PP_CG; ++cc) {
+      const int c = cg0 + cc;
+      if (c >= nc) break;
+      if (cc + 1 < PP_CG && c + 1 < nc) load_c(c + 1, n0, n1);
+      float sk[PP_VB];
+#pragma unroll
+      for (int k = 0; k < PP_VB; ++k) sk[k] = k < nvb ? scale[(vb + k) * ldsc + c] : 0.f;
 #pragma unroll
       for (int k = 0; k < PP_VB; ++k) {
         if (k < nvb) {
-          const float s = scale[(vb + k) * ldsc + c];
+          const float s = sk[k];
 #pragma unroll
           for (int h = 0; h < PP_NH; ++h) {
             if (!one[h]) continue;
@@ -105,6 +161,11 @@ __global__ __launch_bounds__(PP_THREADS) void pair_products_kernel(const float2 
             }
           }
         }
+      }
+#pragma unroll
+      for (int h = 0; h < PP_NH; ++h) {
+        c0[h] = n0[h];
+        c1[h] = n1[h];
       }
     }
   }

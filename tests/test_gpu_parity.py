@@ -44,7 +44,9 @@ def sys_c64(n, nv, nc, r2, seed=0, q=(0.0, 0.0, 0.0)):
 # --- pair products --------------------------------------------------------------------------
 @pytest.mark.parametrize("n,nv,nc,r2", [(12, 8, 64, 10.0),
                                         (5, 3, 7, 3.0),       # odd nr, fewer bands than one block of each
-                                        (6, 11, 13, 4.0)])    # two occupied and two unoccupied blocks, ragged
+                                        (6, 11, 13, 4.0),     # two occupied and two unoccupied blocks, ragged
+                                        (12, 11, 13, 10.0),   # the same raggedness where whole 1024-point chunks exist
+                                        (11, 3, 9, 8.0)])     # odd nr above one chunk: every workgroup on the general path
 def test_pair_products(gw, n, nv, nc, r2):
     s = sys_c64(n, nv, nc, r2)
     f = gw.pair_products(c64(s.psi_v), c64(s.psi_c), s.e_v, s.e_c, prefactor=2.0)
