@@ -9,7 +9,7 @@
 #include <cstring>
 #include <limits>
 #include <new>
-#include <unordered_set>
+#include <utility>
 #include <vector>
 
 #include "gw_internal.h"
@@ -130,19 +130,37 @@ int check_sphere(gw_ctx *ctx, gw_grid g, const int *miller, int ng) {
   GW_CHECK(ctx, miller != nullptr, "g_miller must not be NULL");
   const long long nr = (long long)g.n1 * g.n2 * g.n3;
   GW_CHECK(ctx, ng > 0 && ng <= nr, "ng must be in [1, nr] (got %d)", ng);
-  std::unordered_set<long long> seen;
-  seen.reserve((size_t)ng * 2);
+  const size_t nm = (size_t)ng * 3;
+  // a sphere that passed before on this grid passes again without the scan (a step checks the same
+  // few spheres on every call)
+  for (const gw_ctx::SphereSeen &v : ctx->spheres_ok)
+    if (v.n1 == g.n1 && v.n2 == g.n2 && v.n3 == g.n3 && v.miller.size() == nm &&
+        std::equal(miller, miller + nm, v.miller.begin()))
+      return GW_OK;
   const int n[3] = {g.n1, g.n2, g.n3};
+  std::vector<std::pair<long long, int>> keys((size_t)ng);
   for (int i = 0; i < ng; ++i) {
     long long key = 0;
     for (int d = 0; d < 3; ++d) {
       const int m = miller[3 * i + d];
       GW_CHECK(ctx, 2LL * std::llabs((long long)m) < n[d], "g_miller[%d][%d] = %d violates |m| < n/2 (n = %d)", i, d, m,
                n[d]);
-      key = key * n[d] + ((m % n[d]) + n[d]) % n[d];
+      key = key * n[d] + (m < 0 ? m + n[d] : m);
     }
-    GW_CHECK(ctx, seen.insert(key).second, "g_miller[%d] duplicates an earlier G", i);
+    keys[(size_t)i] = {key, i};
   }
+  // equal keys sort together in index order; every member of a run after its first repeats an earlier G
+  std::sort(keys.begin(), keys.end());
+  int first_dup = -1;
+  for (size_t j = 1; j < keys.size(); ++j)
+    if (keys[j].first == keys[j - 1].first && (first_dup < 0 || keys[j].second < first_dup)) first_dup = keys[j].second;
+  GW_CHECK(ctx, first_dup < 0, "g_miller[%d] duplicates an earlier G", first_dup);
+  gw_ctx::SphereSeen &slot = ctx->spheres_ok[ctx->spheres_next];
+  ctx->spheres_next = (ctx->spheres_next + 1) % (int)(sizeof(ctx->spheres_ok) / sizeof(ctx->spheres_ok[0]));
+  slot.n1 = g.n1;
+  slot.n2 = g.n2;
+  slot.n3 = g.n3;
+  slot.miller.assign(miller, miller + nm);
   return GW_OK;
 }
 

@@ -32,6 +32,10 @@ struct gw_ctx {
   std::string arch;                   // device architecture name (cached)
   // the sphere plan last uploaded into each map slot, reused while grid, Miller list and stream match
   std::map<int, std::unique_ptr<gwi::PlanCacheEntry>> plans;
+  // the last spheres (grid and Miller list) that passed the argument checks, reused round-robin
+  struct SphereSeen { int n1 = 0, n2 = 0, n3 = 0; std::vector<int> miller; };
+  SphereSeen spheres_ok[4];
+  int spheres_next = 0;
 };
 
 namespace gwi {

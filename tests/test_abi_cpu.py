@@ -97,6 +97,19 @@ def test_dry_run_polarizability_checks(gw):
     dup = m.copy(); dup[3] = dup[2]
     _, pdup = i32(dup)
     assert call(m=pdup) == 1 and "duplicates" in d.err()
+    # several repeats: the first index that repeats an earlier G is the one reported
+    dup2 = m.copy(); dup2[9] = dup2[1]; dup2[5] = dup2[4]
+    _, pdup2 = i32(dup2)
+    assert call(m=pdup2) == 1 and "g_miller[5] duplicates" in d.err()
+    # a sphere that passed is remembered by content, not by address: the same buffer edited in place
+    # into a repeat fails again, and passes once restored
+    same = m.copy()
+    _, psame = i32(same)
+    assert call(m=psame) == 0
+    keep = same[6].copy(); same[6] = same[0]
+    assert call(m=psame) == 1 and "g_miller[6] duplicates" in d.err()
+    same[6] = keep
+    assert call(m=psame) == 0
     nyq = m.copy(); nyq[1] = [3, 0, 0]
     _, pnyq = i32(nyq)
     assert call(m=pnyq) == 1 and "|m| < n/2" in d.err()
