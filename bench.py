@@ -73,9 +73,11 @@ def parity_small(gw, torch, prec):
             "eps_inv": orc.rel_f(einv.cpu().numpy(), ei)}
 
 
-PMC_SUMMARIES = [os.path.join(ROOT, "profiles", f) for f in ("herk_bf16split_wide_si36_pmc.md",
+PMC_SUMMARIES = [os.path.join(ROOT, "profiles", f) for f in ("herk_bf16split_planar_si36_pmc.md",
+                                                              "herk_bf16split_wide_si36_pmc.md",
                                                               "herk_bf16split_si36_pmc.md")]
-PMC_KERNEL = {"bf16split_t128x256_wide_k16": "herk_split_wide_kernel<__bf16, false>",
+PMC_KERNEL = {"bf16split_t128x256_planar_k16": "herk_split_wide_planar_kernel<__bf16, false>",
+              "bf16split_t128x256_wide_k16": "herk_split_wide_kernel<__bf16, false>",
               "bf16split_t128_ws2_k32": "herk_split_ws_kernel<__bf16, 32, false, false, 2>"}
 
 

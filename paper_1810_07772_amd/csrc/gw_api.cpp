@@ -403,7 +403,7 @@ int upload_scales(gw_ctx *ctx, const double *e_v, int nv, const double *e_c, int
   void *eb, *sb;
   const int ldsc = scale_ld(nc);
   GW_STATUS(ws_get(ctx, WS_ENERGY, (size_t)(nv + nc) * sizeof(double), &eb, s));
-  GW_STATUS(ws_get(ctx, WS_SCALE, (size_t)nv * ldsc * sizeof(float), &sb, s));
+  GW_STATUS(ws_get(ctx, WS_SCALE, scale_table_floats(nv, nc) * sizeof(float), &sb, s));
   double *de = (double *)eb;
   GW_HIP(ctx, hipMemcpyAsync(de, e_v, nv * sizeof(double), hipMemcpyHostToDevice, s));
   GW_HIP(ctx, hipMemcpyAsync(de + nv, e_c, nc * sizeof(double), hipMemcpyHostToDevice, s));

@@ -123,7 +123,7 @@ int autotune_impl(gw_ctx *ctx, const float2 *psi_v, int nv, const float2 *psi_c,
   const int ldsc = scale_ld(nc);
   void *eb, *sb, *bx;
   GWX_STATUS(api_ws_get(ctx, WS_ENERGY, (size_t)(nv + nc) * sizeof(double), &eb, s));
-  GWX_STATUS(api_ws_get(ctx, WS_SCALE, (size_t)nv * ldsc * sizeof(float), &sb, s));
+  GWX_STATUS(api_ws_get(ctx, WS_SCALE, scale_table_floats(nv, nc) * sizeof(float), &sb, s));
   GWX_STATUS(api_ws_get(ctx, WS_BSCALE, band_exp_ints(nv, nc) * sizeof(int), &bx, s));
   double *de = (double *)eb;
   GWX_HIP(ctx, hipMemcpyAsync(de, e_v, nt * sizeof(double), hipMemcpyHostToDevice, s));
@@ -274,7 +274,7 @@ int gw_polarizability_batched(gw_ctx *ctx, const gw_c32 *psi_occ, int nv, const 
     const int nc = jobs[j].nc, ng = jobs[j].ng;
     const SpherePlan &pl = plans[j];
     void *p[kJobSlots];
-    const size_t bytes[kJobSlots] = {(size_t)(nv + nc) * sizeof(double), (size_t)nv * scale_ld(nc) * sizeof(float),
+    const size_t bytes[kJobSlots] = {(size_t)(nv + nc) * sizeof(double), scale_table_floats(nv, nc) * sizeof(float),
                                      band_exp_ints(nv, nc) * sizeof(int),
                                      pl.maps_ints() * sizeof(int),
                                      (size_t)ng * 3 * sizeof(int), (size_t)ng * sizeof(double)};

@@ -69,6 +69,7 @@ enum SlotId {
 // Kernel launchers.  All return hipSuccess or the launch error; all run on `s`.
 // Pair scales s_vc = sqrt(p / (E_c - E_v)) as float [nv][ldsc], zero for nc <= c < ldsc.
 int scale_ld(int nc);
+size_t scale_table_floats(int nv, int nc);   // s table, then s^2 table, each [nv][scale_ld(nc)]
 hipError_t launch_scale_table(const double *e_v, int nv, const double *e_c, int nc, double prefactor,
                               float *scale, int ldsc, hipStream_t s);
 hipError_t launch_pair_products(const float2 *psi_v, int nv, const float2 *psi_c, int nc, int nr,

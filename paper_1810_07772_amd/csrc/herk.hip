@@ -24,6 +24,8 @@
 //    split kernels are wave-specialised (herk_split_ws_kernel): separate producer waves form
 //    and split f while the MFMA waves run, and the partial sums are added into P every
 //    32768 pairs.
+#include <utility>
+
 #include "gw_internal.h"
 
 namespace gwi {
@@ -950,6 +952,254 @@ __global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_kernel(const floa
 }
 
 // ---------------------------------------------------------------------------------------------
+// Planar wide kernel: the wide kernel's 128 x 256 block and twelve waves, with each stage's pair
+// products stored planar so that the MFMA waves spend no VALU work on their operands.  Within a group
+// of four pairs (one MFMA lane's K slice of eight narrow values) a point holds [Re f x 4, Im f x 4].
+// The real part of an output entry is then dot(A, B) over the slices, and the imaginary part the
+// accumulators carry, ar.bi - ai.br, is dot(A', B) with A' = [-Im f, Re f]: the producers store A'
+// beside A for the 128 row points (row words [Re, Im, -Im, Re] per group), and the 256 column points
+// need no second copy.  Without the FP16 band exponents the row side also carries the whole pair
+// weight s^2 = p / (E_c - E_v) and the column side none, P(r, r') = sum s^2 g(r) conj(g(r')) with
+// g = conj(psi_v) psi_c, the same sum as f(r) conj(f(r')) with two multiplies fewer per column entry.
+// Per thread and stage a producer forms one row point's 8 pairs (its half of the stage) and one
+// column point's 16 pairs.
+// ---------------------------------------------------------------------------------------------
+constexpr int PW_RW = 36;   // 32-bit words per row point and buffer: 4 groups x 8 words, 4 words of padding
+constexpr int PW_CW = 20;   // per column point: 4 groups x [Re, Im] (4 words), 4 words of padding
+constexpr unsigned PW_SIGNS = 0x80008000u;   // the sign bits of both narrow halves of a word
+
+template <typename T, bool SCALED>
+__global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_planar_kernel(
+    const float2 *__restrict__ psi_v, const float2 *__restrict__ psi_c, const float *__restrict__ scale, int ldsc,
+    const int *__restrict__ band_exp, float2 *__restrict__ P, int nr, int nv, int nc, int nblocks, int accumulate) {
+  typedef typename SplitTraits<T>::vec vec;
+  constexpr bool S2 = !SCALED;   // row side weighted by s^2, column side unweighted
+  __shared__ __attribute__((aligned(16))) unsigned sRH[2][HB][PW_RW];
+  __shared__ __attribute__((aligned(16))) unsigned sRL[2][HB][PW_RW];
+  __shared__ __attribute__((aligned(16))) unsigned sCH[2][2 * HB][PW_CW];
+  __shared__ __attribute__((aligned(16))) unsigned sCL[2][2 * HB][PW_CW];
+  const int *order = SCALED ? band_exp + nv : nullptr, *esorted = SCALED ? band_exp + 2 * nv : nullptr;
+
+  int bi, jp;
+  wide_block_of(xcd_remap(blockIdx.x, nblocks), bi, jp);
+  const int I0 = bi * HB, J0 = 2 * jp * HB;
+  const int ncb = (2 * jp + 1 <= bi) ? 2 : 1;          // column blocks of the pair on or below the diagonal
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nchc = (nc + WK - 1) / WK;
+  const int nch = nv * nchc;
+
+  if (wave >= 8) {
+    // ---- producers: row point rpt (pairs 8 rh .. 8 rh + 7 of each stage), column point cpt (all 16)
+    const int pw = wave - 8;
+    const int rpt = lane + 64 * (pw & 1), rh = pw >> 1, cpt = lane + 64 * pw;
+    // points past nr only feed outputs that are never stored: clamp the address
+    const int grow = min(I0 + rpt, nr - 1), gcol = min(J0 + cpt, nr - 1);
+    float2 rc[8], rcn[8], cc[16], ccn[16], pvr, pvc;
+    float sr[8], scl[SCALED ? 16 : 1];
+    auto load_c = [&](float2 (&rd)[8], float2 (&cd)[16], int chunk) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) rd[k] = psi_c[(size_t)min(chunk * WK + 8 * rh + k, nc - 1) * nr + grow];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) cd[k] = psi_c[(size_t)min(chunk * WK + k, nc - 1) * nr + gcol];
+    };
+    auto load_v = [&](int vi, int c0) {                    // psi_v and the weights of stage (vi, c0)
+      const int v = SCALED ? order[vi] : vi;
+      pvr = psi_v[(size_t)v * nr + grow];
+      pvc = psi_v[(size_t)v * nr + gcol];
+      if (SCALED) {
+        const float m = ldexpf(1.0f, esorted[vi]);
+        pvr.x *= m; pvr.y *= m; pvc.x *= m; pvc.y *= m;
+      }
+      // wave-uniform offsets (scalar loads); both tables are zero past nc, so those pairs vanish
+      const float *srow = scale + (S2 ? (size_t)nv * ldsc : 0) + (size_t)v * ldsc + c0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sr[k] = srow[8 * rh + k];
+      if (SCALED) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) scl[k] = srow[k];
+      }
+    };
+    auto produce = [&](int buf) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        float fx[4], fy[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int k = 4 * g + m;
+          fx[m] = (pvr.x * rc[k].x + pvr.y * rc[k].y) * sr[k];
+          fy[m] = (pvr.x * rc[k].y - pvr.y * rc[k].x) * sr[k];
+        }
+        unsigned h[4], l[4];
+        NarrowSplit<T>::split(fx[0], fx[1], h[0], l[0]);
+        NarrowSplit<T>::split(fx[2], fx[3], h[1], l[1]);
+        NarrowSplit<T>::split(fy[0], fy[1], h[2], l[2]);
+        NarrowSplit<T>::split(fy[2], fy[3], h[3], l[3]);
+        u32x4 *dh = reinterpret_cast<u32x4 *>(&sRH[buf][rpt][8 * (2 * rh + g)]);
+        u32x4 *dl = reinterpret_cast<u32x4 *>(&sRL[buf][rpt][8 * (2 * rh + g)]);
+        dh[0] = u32x4{h[0], h[1], h[2], h[3]};
+        dh[1] = u32x4{h[2] ^ PW_SIGNS, h[3] ^ PW_SIGNS, h[0], h[1]};
+        dl[0] = u32x4{l[0], l[1], l[2], l[3]};
+        dl[1] = u32x4{l[2] ^ PW_SIGNS, l[3] ^ PW_SIGNS, l[0], l[1]};
+      }
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        float fx[4], fy[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int k = 4 * g + m;
+          fx[m] = pvc.x * cc[k].x + pvc.y * cc[k].y;
+          fy[m] = pvc.x * cc[k].y - pvc.y * cc[k].x;
+          if (SCALED) { fx[m] *= scl[SCALED ? k : 0]; fy[m] *= scl[SCALED ? k : 0]; }
+        }
+        unsigned h[4], l[4];
+        NarrowSplit<T>::split(fx[0], fx[1], h[0], l[0]);
+        NarrowSplit<T>::split(fx[2], fx[3], h[1], l[1]);
+        NarrowSplit<T>::split(fy[0], fy[1], h[2], l[2]);
+        NarrowSplit<T>::split(fy[2], fy[3], h[3], l[3]);
+        *reinterpret_cast<u32x4 *>(&sCH[buf][cpt][4 * g]) = u32x4{h[0], h[1], h[2], h[3]};
+        *reinterpret_cast<u32x4 *>(&sCL[buf][cpt][4 * g]) = u32x4{l[0], l[1], l[2], l[3]};
+      }
+    };
+    // stage ch is (occupied band ch % nv, unoccupied chunk ch / nv); the indices of stages ch + 1 and
+    // ch + 2 advance by counters
+    int v1 = 1 % nv, v2 = 2 % nv, c2 = 2 / nv;
+    load_c(rc, cc, 0);
+    load_v(0, 0);
+    produce(0);
+    if (nch > 1) load_v(v1, (1 / nv) * WK);
+    if (nv == 1 && nch > 1) load_c(rcn, ccn, 1);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+      if (ch + 1 < nch) {
+        if (v1 == 0) {                                     // stage ch+1 opens the next unoccupied chunk
+#pragma unroll
+          for (int k = 0; k < 8; ++k) rc[k] = rcn[k];
+#pragma unroll
+          for (int k = 0; k < 16; ++k) cc[k] = ccn[k];
+        }
+        produce((ch & 1) ^ 1);
+        if (ch + 2 < nch) {
+          load_v(v2, c2 * WK);
+          if (v2 == 0) load_c(rcn, ccn, c2);
+        }
+      }
+      v1 = v1 + 1 == nv ? 0 : v1 + 1;
+      if (++v2 == nv) { v2 = 0; ++c2; }
+      __syncthreads();
+    }
+    return;
+  }
+
+  // ---- consumers: quadrant rows I0 + 64 wr, columns J0 + 64 wc
+  const int wr = wave >> 2, wc = wave & 3;
+  const bool active = (wc >> 1) < ncb;                     // wave-uniform: this quadrant is on or below the diagonal
+  const int kq = lane >> 5, idx = lane & 31;
+  const int ar0 = wr * 64 + idx, bc0 = wc * 64 + idx;      // LDS rows of the A and B operands
+  f32x16 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) { accR[a][b][e] = 0.f; accI[a][b][e] = 0.f; }
+  auto unscale = [&](int e) {
+    const float f = ldexpf(1.0f, -2 * e);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        accR[a][b] *= f;
+        accI[a][b] *= f;
+      }
+  };
+  constexpr int FOLD_STAGES = FOLD_PAIRS / WK;
+  const int mrow = bi, mcol = 2 * jp + (wc >> 1);          // 128-blocks of this quadrant
+  const bool mirror_q = mcol != mrow;
+  int nfold = 0;
+  // one stage per call; the buffer index is a constant of each copy, so the LDS addresses are immediates
+  auto stage = [&](int ch, auto bufc) {
+    constexpr int buf = decltype(bufc)::value;
+    if (active) {
+      if (SCALED && ch > 0 && (ch % FOLD_STAGES) != 0) {
+        const int vi = ch % nv;
+        const int d = esorted[vi] - esorted[vi == 0 ? nv - 1 : vi - 1];
+        if (d != 0) {
+          const float f = ldexpf(1.0f, 2 * d);
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              accR[a][b] *= f;
+              accI[a][b] *= f;
+            }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < WK / 8; ++g) {
+        const int ao = 8 * (2 * g + kq), bo = 4 * (2 * g + kq);   // this lane half's group of four pairs
+#define GW_PROD4(ACC, A0, A1, B0, B1)                        \
+  ACC[0][0] = SplitTraits<T>::mfma(A0, B0, ACC[0][0]);        \
+  ACC[0][1] = SplitTraits<T>::mfma(A0, B1, ACC[0][1]);        \
+  ACC[1][0] = SplitTraits<T>::mfma(A1, B0, ACC[1][0]);        \
+  ACC[1][1] = SplitTraits<T>::mfma(A1, B1, ACC[1][1]);
+        // at most three operand pairs live: A hi, B hi and one of A lo, A' lo, A' hi; then B lo
+        const vec ah0 = *reinterpret_cast<const vec *>(&sRH[buf][ar0][ao]);
+        const vec ah1 = *reinterpret_cast<const vec *>(&sRH[buf][ar0 + 32][ao]);
+        vec b0 = *reinterpret_cast<const vec *>(&sCH[buf][bc0][bo]);
+        vec b1 = *reinterpret_cast<const vec *>(&sCH[buf][bc0 + 32][bo]);
+        GW_PROD4(accR, ah0, ah1, b0, b1)           // hi * hi
+        {
+          const vec al0 = *reinterpret_cast<const vec *>(&sRL[buf][ar0][ao]);
+          const vec al1 = *reinterpret_cast<const vec *>(&sRL[buf][ar0 + 32][ao]);
+          GW_PROD4(accR, al0, al1, b0, b1)         // lo * hi
+        }
+        {
+          const vec xl0 = *reinterpret_cast<const vec *>(&sRL[buf][ar0][ao + 4]);
+          const vec xl1 = *reinterpret_cast<const vec *>(&sRL[buf][ar0 + 32][ao + 4]);
+          GW_PROD4(accI, xl0, xl1, b0, b1)         // lo' * hi
+        }
+        const vec xh0 = *reinterpret_cast<const vec *>(&sRH[buf][ar0][ao + 4]);
+        const vec xh1 = *reinterpret_cast<const vec *>(&sRH[buf][ar0 + 32][ao + 4]);
+        GW_PROD4(accI, xh0, xh1, b0, b1)           // hi' * hi
+        b0 = *reinterpret_cast<const vec *>(&sCL[buf][bc0][bo]);
+        b1 = *reinterpret_cast<const vec *>(&sCL[buf][bc0 + 32][bo]);
+        GW_PROD4(accR, ah0, ah1, b0, b1)           // hi * lo
+        GW_PROD4(accI, xh0, xh1, b0, b1)           // hi' * lo
+#undef GW_PROD4
+      }
+      // FOLD_STAGES is even, so a fold follows only odd stages, which use buffer 1
+      if (buf == 1 && (ch + 1) % FOLD_STAGES == 0 && ch + 1 < nch) {
+        if (SCALED) unscale(esorted[ch % nv]);
+        int lane_f = lane;
+        asm volatile("" : "+v"(lane_f));
+        store_tile(P, nr, I0, J0, accumulate && mirror_q, accumulate || nfold > 0, accR, accI, wr, wc, lane_f);
+        ++nfold;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) { accR[a][b][e] = 0.f; accI[a][b][e] = 0.f; }
+      }
+    }
+    __syncthreads();
+  };
+  static_assert(FOLD_STAGES % 2 == 0, "folds must follow odd stages");
+  __syncthreads();
+  int ch = 0;
+  for (; ch + 1 < nch; ch += 2) {
+    stage(ch, std::integral_constant<int, 0>{});
+    stage(ch + 1, std::integral_constant<int, 1>{});
+  }
+  if (ch < nch) stage(ch, std::integral_constant<int, 0>{});
+  if (!active) return;
+  if (SCALED) unscale(esorted[(nch - 1) % nv]);
+  if (nfold == 0 || accumulate) store_tile(P, nr, I0, J0, mirror_q, accumulate || nfold > 0, accR, accI, wr, wc, lane);
+  else store_tile_after_folds(P, nr, I0, J0, mirror_q, accR, accI, wr, wc, lane);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Per-band exponents of the FP16 path: e_v = floor(log2(2^14 / bound_v)) with
 // bound_v = max_r |psi_v(r)| * max_{c,r} |psi_c(r)| * max_c s_vc >= max |f_vc(r)|, so the
 // scaled f of band v stays below 2^14 (FP16 max 65504) and its lo part stays normal for
@@ -1084,6 +1334,8 @@ static const TileCfg kTiles[] = {
   {"fp16split_t128_ws2_k32_scaled", GW_SPLIT_FP16_SCALED},
   {"bf16split_t128x256_wide_k16", GW_SPLIT_BF16},
   {"fp16split_t128x256_wide_k16_scaled", GW_SPLIT_FP16_SCALED},
+  {"bf16split_t128x256_planar_k16", GW_SPLIT_BF16},
+  {"fp16split_t128x256_planar_k16_scaled", GW_SPLIT_FP16_SCALED},
 };
 
 int herk_tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -1095,8 +1347,8 @@ int herk_default_tile(int precision, int nr) {
   (void)nr;
   switch (precision) {
     case GW_FP32: return 4;
-    case GW_SPLIT_BF16: return 13;
-    case GW_SPLIT_FP16_SCALED: return 14;
+    case GW_SPLIT_BF16: return 15;
+    case GW_SPLIT_FP16_SCALED: return 16;
   }
   return -1;
 }
@@ -1146,6 +1398,19 @@ hipError_t launch_herk(int precision, int tile, const float2 *psi_v, const float
       else
         hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_wide_kernel<_Float16, true>), dim3(nw), dim3(3 * NTHR), 0, s,
                            psi_v, psi_c, scale, ldsc, band_exp, p, nr, nv, nc, nw, accumulate);
+      break;
+    }
+    case 15:
+    case 16: {
+      // the BF16 instance reads the s^2 table that follows the s table (scale_table_floats)
+      const int nw = wide_block_count(nb);
+      if (tile == 16 && !band_exp) return hipErrorInvalidValue;
+      if (tile == 15)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_wide_planar_kernel<__bf16, false>), dim3(nw), dim3(3 * NTHR), 0,
+                           s, psi_v, psi_c, scale, ldsc, band_exp, p, nr, nv, nc, nw, accumulate);
+      else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(herk_split_wide_planar_kernel<_Float16, true>), dim3(nw), dim3(3 * NTHR), 0,
+                           s, psi_v, psi_c, scale, ldsc, band_exp, p, nr, nv, nc, nw, accumulate);
       break;
     }
     default:

@@ -44,7 +44,7 @@ static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 // Bytes of scratch one call needs: energies, the scale table, the band exponents (FP16 only).
 size_t noalloc_scratch_bytes(int nv, int nc, int precision) {
   size_t b = round256((size_t)(nv + nc) * sizeof(double));
-  b += round256((size_t)nv * scale_ld(nc) * sizeof(float));
+  b += round256(scale_table_floats(nv, nc) * sizeof(float));
   if (precision == GW_SPLIT_FP16_SCALED) b += round256(band_exp_ints(nv, nc) * sizeof(int));
   return b;
 }
@@ -83,7 +83,7 @@ extern "C" int gw_polarizability_r_noalloc(gw_ctx *ctx, const gw_c32 *psi_v, int
   size_t off = round256((size_t)(nv + nc) * sizeof(double));
   float *scale = reinterpret_cast<float *>(base + off);
   const int ldsc = scale_ld(nc);
-  off += round256((size_t)nv * ldsc * sizeof(float));
+  off += round256(scale_table_floats(nv, nc) * sizeof(float));
   int *bexp = o.precision == GW_SPLIT_FP16_SCALED ? reinterpret_cast<int *>(base + off) : nullptr;
   GWX_HIP(ctx, hipMemcpyAsync(energy, e_v, (size_t)nv * sizeof(double), hipMemcpyHostToDevice, s));
   GWX_HIP(ctx, hipMemcpyAsync(energy + nv, e_c, (size_t)nc * sizeof(double), hipMemcpyHostToDevice, s));

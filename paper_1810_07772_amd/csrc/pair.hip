@@ -11,13 +11,18 @@
 namespace gwi {
 
 int scale_ld(int nc) { return (nc + 31) / 32 * 32; }
+size_t scale_table_floats(int nv, int nc) { return (size_t)2 * nv * scale_ld(nc); }
 
+// s_vc = sqrt(p / (E_c - E_v)) in [nv][ldsc], then s_vc^2 = p / (E_c - E_v) in a second [nv][ldsc] table
+// (the planar wide update scales only its row side, by s^2); zero for c >= nc in both
 __global__ void scale_table_kernel(const double *__restrict__ e_v, int nv, const double *__restrict__ e_c, int nc,
                                    double prefactor, float *__restrict__ scale, int ldsc) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nv * ldsc) return;
   const int v = idx / ldsc, c = idx - v * ldsc;
-  scale[idx] = c < nc ? (float)sqrt(prefactor / (e_c[c] - e_v[v])) : 0.0f;
+  const double q = c < nc ? prefactor / (e_c[c] - e_v[v]) : 0.0;
+  scale[idx] = (float)sqrt(q);
+  scale[(size_t)nv * ldsc + idx] = (float)q;
 }
 
 hipError_t launch_scale_table(const double *e_v, int nv, const double *e_c, int nc, double prefactor, float *scale,

@@ -338,7 +338,8 @@ def test_fp16_scaled_tiles_agree_with_wide_band_exponents(gw):
     a = gw.polarizability_r(pv, pc, e_v, s.e_c, precision="fp16", tile=t_old).cpu().numpy()
     ref = orc.polarizability_r(s.psi_v, s.psi_c, e_v, s.e_c)
     ea = orc.rel_f(a, ref)
-    for ws in ("fp16split_t128_ws_k32_scaled", "fp16split_t128_ws2_k32_scaled", "fp16split_t128x256_wide_k16_scaled"):
+    for ws in ("fp16split_t128_ws_k32_scaled", "fp16split_t128_ws2_k32_scaled", "fp16split_t128x256_wide_k16_scaled",
+               "fp16split_t128x256_planar_k16_scaled"):
         b = gw.polarizability_r(pv, pc, e_v, s.e_c, precision="fp16", tile=names.index(ws)).cpu().numpy()
         eb, eab = orc.rel_f(b, ref), orc.rel_f(b, a)
         print(f"fp16 per-band fold {ea:.2e}, {ws} with rescaling {eb:.2e}, between them {eab:.2e}")
@@ -351,9 +352,11 @@ def test_fp16_scaled_tiles_agree_with_wide_band_exponents(gw):
                                                 ("bf16", "bf16split_t128_ws", 1e-4),
                                                 ("bf16", "bf16split_t128_ws2_k32", 1e-4),
                                                 ("bf16", "bf16split_t128x256_wide_k16", 1e-4),
+                                                ("bf16", "bf16split_t128x256_planar_k16", 1e-4),
                                                 ("fp16", "fp16split_t128_ws_k32_scaled", 2e-5),
                                                 ("fp16", "fp16split_t128_ws2_k32_scaled", 2e-5),
-                                                ("fp16", "fp16split_t128x256_wide_k16_scaled", 2e-5)])
+                                                ("fp16", "fp16split_t128x256_wide_k16_scaled", 2e-5),
+                                                ("fp16", "fp16split_t128x256_planar_k16_scaled", 2e-5)])
 @pytest.mark.parametrize("nv,nc", [(32, 1024), (64, 600), (64, 1024)])
 def test_split_two_level_sum(gw, prec, tile_name, tol, nv, nc):
     """K = nv*nc of 32768 (no fold), 38400 (one fold, ragged) and 65536 (a fold between two full blocks)
