@@ -76,19 +76,48 @@ __global__ __launch_bounds__(256, 4) void zgemm_kernel(int M, int N, int K, cons
   };
   // Loads keep the raw values; the conjugation of a transposed operand is applied when they are
   // written to LDS, so no instruction waits on a load before the stage's MFMAs have been issued.
+  // Each thread's elements advance by GK along k per stage: running pointers, and no bounds test in
+  // the stages of a whole tile that lie inside [kbeg, kend).
+  const double2 *pa[PER], *pb[PER];
+  int ka[PER], kb[PER];
+  bool ra[PER], cb_ok[PER];
+#pragma unroll
+  for (int it = 0; it < PER; ++it) {
+    const int idx = tid + it * 256;
+    int r, c, kk;
+    a_coord(idx, r, kk);
+    ka[it] = kk;
+    ra[it] = row0 + r < M;
+    const int rr = min(row0 + r, M - 1);   // an address inside A for rows past M (never read)
+    pa[it] = transA ? A + (long long)(kbeg + kk) * lda + rr : A + (long long)rr * lda + kbeg + kk;
+    b_coord(idx, c, kk);
+    kb[it] = kk;
+    cb_ok[it] = col0 + c < N;
+    const int cc = min(col0 + c, N - 1);
+    pb[it] = transB ? B + (long long)cc * ldb + kbeg + kk : B + (long long)(kbeg + kk) * ldb + cc;
+  }
+  const long long step_a = transA ? (long long)GK * lda : GK, step_b = transB ? GK : (long long)GK * ldb;
+  const bool whole = row0 + GT <= M && col0 + GT <= N;
   auto gload = [&](int k0) {
+    if (whole && k0 + GK <= kend) {        // uniform
+#pragma unroll
+      for (int it = 0; it < PER; ++it) {
+        va[it] = *pa[it];
+        vb[it] = *pb[it];
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < PER; ++it) {
+        va[it] = make_double2(0.0, 0.0);
+        if (ra[it] && k0 + ka[it] < kend) va[it] = *pa[it];
+        vb[it] = make_double2(0.0, 0.0);
+        if (cb_ok[it] && k0 + kb[it] < kend) vb[it] = *pb[it];
+      }
+    }
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
-      const int idx = tid + it * 256;
-      int r, c, kk;
-      a_coord(idx, r, kk);
-      va[it] = make_double2(0.0, 0.0);
-      if (row0 + r < M && k0 + kk < kend)
-        va[it] = transA ? A[(long long)(k0 + kk) * lda + row0 + r] : A[(long long)(row0 + r) * lda + k0 + kk];
-      b_coord(idx, c, kk);
-      vb[it] = make_double2(0.0, 0.0);
-      if (col0 + c < N && k0 + kk < kend)
-        vb[it] = transB ? B[(long long)(col0 + c) * ldb + k0 + kk] : B[(long long)(k0 + kk) * ldb + col0 + c];
+      pa[it] += step_a;
+      pb[it] += step_b;
     }
   };
   auto lstore = [&](int buf) {
@@ -119,9 +148,11 @@ __global__ __launch_bounds__(256, 4) void zgemm_kernel(int M, int N, int K, cons
       const int kk = 2 * s + (kl >> 1), comp = kl & 1;
       const double a0 = sA[buf][kk][comp][wr * 32 + li], a1 = sA[buf][kk][comp][wr * 32 + 16 + li];
       const double x0 = sX[buf][kk][comp][wc * 32 + li], x1 = sX[buf][kk][comp][wc * 32 + 16 + li];
-      // Y = [Im B; Re B] = [-X_1; X_0]
+      // Y = [Im B; Re B] = [-X_1; X_0]: the sign flip of the comp = 0 lanes as one xor of the high word
       const double ys0 = sX[buf][kk][comp ^ 1][wc * 32 + li], ys1 = sX[buf][kk][comp ^ 1][wc * 32 + 16 + li];
-      const double y0 = comp ? ys0 : -ys0, y1 = comp ? ys1 : -ys1;
+      const unsigned long long flip = comp ? 0ull : 0x8000000000000000ull;
+      const double y0 = __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, ys0) ^ flip);
+      const double y1 = __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, ys1) ^ flip);
       accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0, accR[0][0], 0, 0, 0);
       accI[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, y0, accI[0][0], 0, 0, 0);
       accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x1, accR[0][1], 0, 0, 0);
