@@ -155,6 +155,7 @@ int check_sphere(gw_ctx *ctx, gw_grid g, const int *miller, int ng) {
   for (size_t j = 1; j < keys.size(); ++j)
     if (keys[j].first == keys[j - 1].first && (first_dup < 0 || keys[j].second < first_dup)) first_dup = keys[j].second;
   GW_CHECK(ctx, first_dup < 0, "g_miller[%d] duplicates an earlier G", first_dup);
+  if (ng > (1 << 20)) return GW_OK;   // spheres this large are checked on every call rather than copied
   gw_ctx::SphereSeen &slot = ctx->spheres_ok[ctx->spheres_next];
   ctx->spheres_next = (ctx->spheres_next + 1) % (int)(sizeof(ctx->spheres_ok) / sizeof(ctx->spheres_ok[0]));
   slot.n1 = g.n1;
