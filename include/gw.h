@@ -158,7 +158,7 @@ int gw_polarizability_r(gw_ctx *ctx, const gw_c32 *psi_v, int nv, const gw_c32 *
  * and the FP16 band exponents go to a fixed 8 MiB device array that each GPU holds
  * for the life of the process (its address is resolved once per device by
  * gw_create): calls needing more than 8 MiB, i.e. about
- * 8 (nv + nc) + 8 nv ceil32(nc) (+ 4 (4 nv + nc) for FP16) bytes, return
+ * 8 (nv + nc) + 8 nv ceil32(nc) (+ 4 (5 nv + nc) for FP16) bytes, return
  * GW_E_INVAL with the figure in gw_last_error.  Every call on one GPU shares that
  * array, so calls that overlap on one GPU (different streams or host threads)
  * race; calls on one stream are ordered.  No hipMalloc, hipFree or other

@@ -958,9 +958,10 @@ __global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_kernel(const floa
 // The real part of an output entry is then dot(A, B) over the slices, and the imaginary part the
 // accumulators carry, ar.bi - ai.br, is dot(A', B) with A' = [-Im f, Re f]: the producers store A'
 // beside A for the 128 row points (row words [Re, Im, -Im, Re] per group), and the 256 column points
-// need no second copy.  Without the FP16 band exponents the row side also carries the whole pair
-// weight s^2 = p / (E_c - E_v) and the column side none, P(r, r') = sum s^2 g(r) conj(g(r')) with
-// g = conj(psi_v) psi_c, the same sum as f(r) conj(f(r')) with two multiplies fewer per column entry.
+// need no second copy.  The row side also carries the whole pair weight s^2 = p / (E_c - E_v) and the
+// column side none, P(r, r') = sum s^2 g(r) conj(g(r')) with g = conj(psi_v) psi_c, the same sum as
+// f(r) conj(f(r')) with two multiplies fewer per column entry; the FP16 instance scales the two sides
+// by 2^{e_v -+ shift_v} (launch_band_exponents), which keeps both in range.
 // Per thread and stage a producer forms one row point's 8 pairs (its half of the stage) and one
 // column point's 16 pairs.
 // ---------------------------------------------------------------------------------------------
@@ -973,12 +974,12 @@ __global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_planar_kernel(
     const float2 *__restrict__ psi_v, const float2 *__restrict__ psi_c, const float *__restrict__ scale, int ldsc,
     const int *__restrict__ band_exp, float2 *__restrict__ P, int nr, int nv, int nc, int nblocks, int accumulate) {
   typedef typename SplitTraits<T>::vec vec;
-  constexpr bool S2 = !SCALED;   // row side weighted by s^2, column side unweighted
   __shared__ __attribute__((aligned(16))) unsigned sRH[2][HB][PW_RW];
   __shared__ __attribute__((aligned(16))) unsigned sRL[2][HB][PW_RW];
   __shared__ __attribute__((aligned(16))) unsigned sCH[2][2 * HB][PW_CW];
   __shared__ __attribute__((aligned(16))) unsigned sCL[2][2 * HB][PW_CW];
   const int *order = SCALED ? band_exp + nv : nullptr, *esorted = SCALED ? band_exp + 2 * nv : nullptr;
+  const int *bshift = SCALED ? band_exp + 4 * nv + nc : nullptr;
 
   int bi, jp;
   wide_block_of(xcd_remap(blockIdx.x, nblocks), bi, jp);
@@ -996,7 +997,7 @@ __global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_planar_kernel(
     // points past nr only feed outputs that are never stored: clamp the address
     const int grow = min(I0 + rpt, nr - 1), gcol = min(J0 + cpt, nr - 1);
     float2 rc[8], rcn[8], cc[16], ccn[16], pvr, pvc;
-    float sr[8], scl[SCALED ? 16 : 1];
+    float sr[8];
     auto load_c = [&](float2 (&rd)[8], float2 (&cd)[16], int chunk) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) rd[k] = psi_c[(size_t)min(chunk * WK + 8 * rh + k, nc - 1) * nr + grow];
@@ -1007,18 +1008,14 @@ __global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_planar_kernel(
       const int v = SCALED ? order[vi] : vi;
       pvr = psi_v[(size_t)v * nr + grow];
       pvc = psi_v[(size_t)v * nr + gcol];
-      if (SCALED) {
-        const float m = ldexpf(1.0f, esorted[vi]);
-        pvr.x *= m; pvr.y *= m; pvc.x *= m; pvc.y *= m;
+      if (SCALED) {                         // rows 2^{e - shift}, columns 2^{e + shift}
+        const float mr = ldexpf(1.0f, esorted[vi] - bshift[v]), mc = ldexpf(1.0f, esorted[vi] + bshift[v]);
+        pvr.x *= mr; pvr.y *= mr; pvc.x *= mc; pvc.y *= mc;
       }
-      // wave-uniform offsets (scalar loads); both tables are zero past nc, so those pairs vanish
-      const float *srow = scale + (S2 ? (size_t)nv * ldsc : 0) + (size_t)v * ldsc + c0;
+      // the s^2 table (wave-uniform offsets: scalar loads); zero past nc, so those pairs vanish
+      const float *srow = scale + (size_t)nv * ldsc + (size_t)v * ldsc + c0;
 #pragma unroll
       for (int k = 0; k < 8; ++k) sr[k] = srow[8 * rh + k];
-      if (SCALED) {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) scl[k] = srow[k];
-      }
     };
     auto produce = [&](int buf) {
 #pragma unroll
@@ -1050,7 +1047,6 @@ __global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_planar_kernel(
           const int k = 4 * g + m;
           fx[m] = pvc.x * cc[k].x + pvc.y * cc[k].y;
           fy[m] = pvc.x * cc[k].y - pvc.y * cc[k].x;
-          if (SCALED) { fx[m] *= scl[SCALED ? k : 0]; fy[m] *= scl[SCALED ? k : 0]; }
         }
         unsigned h[4], l[4];
         NarrowSplit<T>::split(fx[0], fx[1], h[0], l[0]);
@@ -1222,8 +1218,12 @@ __global__ void absmax_rows_kernel(const float2 *__restrict__ psi, int nrows, in
   if (threadIdx.x == 0) out[row] = red[0];
 }
 
+// shift[v] = floor(log2(max_c s_vc)): the planar kernel carries the whole weight s^2 on its row side and
+// none on its column side, and scales them by 2^{e_v - shift_v} and 2^{e_v + shift_v}, so both stay
+// within a factor 2 of the bound above (below 2^15) and their product keeps the factor 2^{2 e_v}.
 __global__ void band_exponent_kernel(const float *__restrict__ vmax, int nv, const float *__restrict__ cmax, int nc,
-                                     const float *__restrict__ scale, int ldsc, int *__restrict__ band_exp) {
+                                     const float *__restrict__ scale, int ldsc, int *__restrict__ band_exp,
+                                     int *__restrict__ shift) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nv) return;
   float cm = 0.f, sm = 0.f;
@@ -1232,6 +1232,7 @@ __global__ void band_exponent_kernel(const float *__restrict__ vmax, int nv, con
   int e = 0;
   if (bound > 0.f) e = (int)floorf(log2f(16384.0f / bound));
   band_exp[v] = max(-60, min(60, e));
+  shift[v] = sm > 0.f ? max(-30, min(30, (int)floorf(log2f(sm)))) : 0;
 }
 
 // Bands ordered by exponent (a stable counting sort over the clamped range [-60, 60], one thread):
@@ -1251,18 +1252,18 @@ __global__ void band_order_kernel(const int *__restrict__ band_exp, int nv, int 
   }
 }
 
-size_t band_exp_ints(int nv, int nc) { return (size_t)4 * nv + nc; }
+size_t band_exp_ints(int nv, int nc) { return (size_t)5 * nv + nc; }
 
 hipError_t launch_band_exponents(const float2 *psi_v, int nv, const float2 *psi_c, int nc, int nr,
                                  const float *scale, int ldsc, int *band_exp, hipStream_t s) {
   // layout (band_exp_ints): exponents [nv], band order [nv], sorted exponents [nv], then the row
-  // maxima as floats: occupied [nv], unoccupied [nc]
+  // maxima as floats: occupied [nv], unoccupied [nc], then the per-band shifts [nv]
   float *vmax = reinterpret_cast<float *>(band_exp + 3 * nv);
   float *cmax = vmax + nv;
   hipLaunchKernelGGL(absmax_rows_kernel, dim3(nv), dim3(256), 0, s, psi_v, nv, nr, vmax);
   hipLaunchKernelGGL(absmax_rows_kernel, dim3(nc), dim3(256), 0, s, psi_c, nc, nr, cmax);
   hipLaunchKernelGGL(band_exponent_kernel, dim3((nv + 63) / 64), dim3(64), 0, s, vmax, nv, cmax, nc, scale, ldsc,
-                     band_exp);
+                     band_exp, band_exp + 4 * nv + nc);
   hipLaunchKernelGGL(band_order_kernel, dim3(1), dim3(64), 0, s, band_exp, nv, band_exp + nv, band_exp + 2 * nv);
   return hipGetLastError();
 }
