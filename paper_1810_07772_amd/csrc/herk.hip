@@ -253,6 +253,7 @@ constexpr int KS = 16;             // pairs per stage
 constexpr int SROW = 2 * KS + 8;   // narrow elements per grid-point row (padded against bank conflicts)
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 template <typename T> struct SplitTraits;
 template <> struct SplitTraits<__bf16> {
@@ -1035,9 +1036,16 @@ __global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_planar_kernel(
         u32x4 *dh = reinterpret_cast<u32x4 *>(&sRH[buf][rpt][8 * (2 * rh + g)]);
         u32x4 *dl = reinterpret_cast<u32x4 *>(&sRL[buf][rpt][8 * (2 * rh + g)]);
         dh[0] = u32x4{h[0], h[1], h[2], h[3]};
-        dh[1] = u32x4{h[2] ^ PW_SIGNS, h[3] ^ PW_SIGNS, h[0], h[1]};
         dl[0] = u32x4{l[0], l[1], l[2], l[3]};
-        dl[1] = u32x4{l[2] ^ PW_SIGNS, l[3] ^ PW_SIGNS, l[0], l[1]};
+        // [-Im, Re] as two 8-byte LDS stores, the second from the registers just stored: one 16-byte store
+        // would need [-Im, Re] in four consecutive registers, i.e. eight moves per stage.  The stores are
+        // volatile only so that they are not merged back into that 16-byte form.
+        typedef __attribute__((address_space(3))) volatile u32x2 lds_u32x2;
+        lds_u32x2 *eh = (lds_u32x2 *)(dh + 1), *el = (lds_u32x2 *)(dl + 1);
+        eh[0] = u32x2{h[2] ^ PW_SIGNS, h[3] ^ PW_SIGNS};
+        eh[1] = u32x2{h[0], h[1]};
+        el[0] = u32x2{l[2] ^ PW_SIGNS, l[3] ^ PW_SIGNS};
+        el[1] = u32x2{l[0], l[1]};
       }
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
