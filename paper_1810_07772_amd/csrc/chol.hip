@@ -261,6 +261,8 @@ hipError_t launch_zgemm(int M, int N, int K, const double2 *A, long long lda, in
 // matrix spreads over about 250 CUs (64 rows per workgroup left three quarters of the CUs idle).
 constexpr int NB = 32;
 constexpr int PR = 16;    // panel rows per workgroup of the diagonal-block kernel
+constexpr int CHOL_PW = 128;   // panel width of the factorisation and the substitution
+constexpr int PD_THREADS = PR * NB;   // diagonal-block kernel: eight waves, one panel entry per thread
 
 // 1 / d for a positive finite d: the hardware estimate refined by two Newton steps r <- r + r (1 - d r),
 // each of which squares the relative error (within an ulp or two of the rounded quotient); three
@@ -278,33 +280,71 @@ __device__ __forceinline__ void static_for(F &&f, std::integer_sequence<int, J..
   (f(std::integral_constant<int, J>{}), ...);
 }
 
-__global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restrict__ A, int n, int k0,
-                                                         double2 *__restrict__ L, double2 *__restrict__ linv,
-                                                         int *__restrict__ pivot) {
+__global__ __launch_bounds__(PD_THREADS) void potrf_diag_kernel(const double2 *__restrict__ A, int n, int p0,
+                                                                int k0, double2 *__restrict__ L,
+                                                                double2 *__restrict__ linv, int *__restrict__ pivot) {
   __shared__ double2 a[NB][NB + 1];
+  __shared__ double2 lb[NB][CHOL_PW - NB + 1];   // L[k0 + i][p0 + k]: the block's rows, earlier panel columns
+  __shared__ double2 lr[PR][CHOL_PW - NB + 1];   // the same columns of this workgroup's panel rows
   __shared__ double2 x[NB][NB + 1];
   __shared__ double2 pa[PR][NB + 1];
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int nb = min(NB, n - k0);
   // this workgroup's PR panel rows below the block, loaded now so that their latency overlaps the
-  // factorisation: thread (pib, pj) holds A[r0 + pib + 8t][k0 + pj]
+  // factorisation: thread (pib, pj) holds A[r0 + pib][k0 + pj]
   const int r0 = k0 + nb + (int)blockIdx.x * PR;
   const int pj = tid % NB, pib = tid / NB;
-  double2 pv[PR * NB / 256];
-#pragma unroll
-  for (int t = 0; t < PR * NB / 256; ++t) {
-    const int r = r0 + pib + 8 * t;
-    pv[t] = (r < n && pj < nb) ? A[(size_t)r * n + k0 + pj] : make_double2(0.0, 0.0);
-  }
+  static_assert(PR * NB == PD_THREADS, "one panel entry per thread");
+  double2 pv = (r0 + pib < n && pj < nb) ? A[(size_t)(r0 + pib) * n + k0 + pj] : make_double2(0.0, 0.0);
   if (tid == 0) bad = 0;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
+  for (int idx = tid; idx < NB * NB; idx += PD_THREADS) {
     const int i = idx / NB, j = idx % NB;
     double2 v = make_double2(0.0, 0.0);
     if (i < nb && j < nb && j <= i) v = A[(size_t)(k0 + i) * n + k0 + j];
     if (i >= nb && i == j) v = make_double2(1.0, 0.0);      // pad with identity
     a[i][j] = v;
     x[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  // Left-looking inside the panel: the kp = k0 - p0 columns of this panel factored by the earlier steps
+  // are applied here, A[k0:, k0:k0+nb] -= L[k0:, p0:k0] L[k0:k0+nb, p0:k0]^H, to this workgroup's copy of
+  // the diagonal block and to its panel rows, instead of by a separate product after every step.  One
+  // panel entry per thread and the block's 528 lower entries over the eight waves.
+  const int kp = k0 - p0;
+  if (kp > 0) {
+    for (int idx = tid; idx < NB * kp; idx += PD_THREADS) {
+      const int i = idx / kp, k = idx % kp;
+      lb[i][k] = i < nb ? L[(size_t)(k0 + i) * n + p0 + k] : make_double2(0.0, 0.0);
+    }
+    for (int idx = tid; idx < PR * kp; idx += PD_THREADS) {
+      const int i = idx / kp, k = idx % kp;
+      lr[i][k] = r0 + i < n ? L[(size_t)(r0 + i) * n + p0 + k] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+    for (int k = 0; k < kp; ++k) {
+      const double2 u = lr[pib][k], w = lb[pj][k];
+      acc.x += u.x * w.x + u.y * w.y;
+      acc.y += u.y * w.x - u.x * w.y;
+    }
+    pv.x -= acc.x;
+    pv.y -= acc.y;
+    for (int e = tid; e < NB * (NB + 1) / 2; e += PD_THREADS) {   // lower entries, numbered row by row
+      int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+      while ((i + 1) * (i + 2) / 2 <= e) ++i;
+      while (i * (i + 1) / 2 > e) --i;
+      const int j = e - i * (i + 1) / 2;
+      double2 ad = make_double2(0.0, 0.0);
+#pragma unroll 4
+      for (int k = 0; k < kp; ++k) {
+        const double2 u = lb[i][k], w = lb[j][k];
+        ad.x += u.x * w.x + u.y * w.y;
+        ad.y += u.y * w.x - u.x * w.y;
+      }
+      a[i][j].x -= ad.x;
+      a[i][j].y -= ad.y;
+    }
   }
   // Unblocked right-looking Cholesky on the lower triangle, with unscaled columns: step j subtracts
   // s_j s_j^H / d_j (d_j the pivot, s_j column j) from the trailing lower triangle.  In elimination form
@@ -313,57 +353,67 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
   // m <= j where row j is non-zero.  After the last step X = Lu^-1, and L = Lu D^1/2, L^-1 = D^-1/2 X
   // follow by scaling.
   //
-  // The 32 steps form the kernel's latency chain.  The block lives in registers, spread over all four
-  // waves: lane (m, c) = (tid % 32, tid / 32) keeps one column on the rows i = 8t + c, so each lane
-  // updates four rows per step.  Column m of A changes only in the steps j < m and column m of X only in
-  // the steps j >= m (X is I on it until then), so the lanes of column m hold A's column until step m,
-  // where they pass it on and take X's identity column in its place.  Step j's column of the factor and
-  // row of X go to LDS rows of their own (colj[j], xrowj[j]), so one barrier per step orders the writes
-  // before the reads and no step overwrites what another still reads.  Every lane then subtracts
-  // s_j(i) w on its rows i > j, with w = conj(s_j(m)) / d_j while it holds A (m > j) and X[j][m] / d_j
-  // once it holds X.  On A's columns this also writes rows j < i < m above the diagonal; those rows are
-  // never read, and X's column is zeroed above its diagonal when it is stored.
+  // The 32 steps form the kernel's latency chain.  The block lives in registers, spread over the first
+  // four waves (the other four only take part in the barriers): lane (m, c) = (tid % 32, tid / 32) keeps
+  // one column on the rows i = 8t + c, so each lane updates four rows per step.  Column m of A changes
+  // only in the steps j < m and column m of X only in the steps j >= m (X is I on it until then), so the
+  // lanes of column m hold A's column until step m, where they pass it on and take X's identity column
+  // in its place.  Step j's column of the factor and row of X go to LDS rows of their own (colj[j],
+  // xrowj[j]), so one barrier per step orders the writes before the reads and no step overwrites what
+  // another still reads.  Every lane then subtracts s_j(i) w on its rows i > j, with w = conj(s_j(m)) / d_j
+  // while it holds A (m > j) and X[j][m] / d_j once it holds X.  On A's columns this also writes rows
+  // j < i < m above the diagonal; those rows are never read, and X's column is zeroed above its diagonal
+  // when it is stored.
   __shared__ double2 colj[NB][NB + 1], xrowj[NB][NB + 1];
   {
     constexpr int C = 8, T = NB / C;                        // row classes, rows per lane
     const int m = tid % NB, c = tid / NB;
+    const bool fw = c < C;                                  // wave-uniform: one of the factoring waves
     double2 z[T];
     __syncthreads();
+    if (fw) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) z[t] = a[C * t + c][m];
+      for (int t = 0; t < T; ++t) z[t] = a[C * t + c][m];
+    }
     int badj = 0;
     auto step = [&](auto jc) {                                 // step j, a compile-time index
       constexpr int j = decltype(jc)::value, jt = j / C, jr = j % C;
-      if (m == j) {
+      if (fw) {
+        if (m == j) {
 #pragma unroll
-        for (int t = jt; t < T; ++t) colj[j][C * t + c] = z[t];     // column j, final from here on
+          for (int t = jt; t < T; ++t) colj[j][C * t + c] = z[t];     // column j, final from here on
 #pragma unroll
-        for (int t = jt; t < T; ++t) z[t] = make_double2(C * t + c == m ? 1.0 : 0.0, 0.0);   // X's column
+          for (int t = jt; t < T; ++t) z[t] = make_double2(C * t + c == m ? 1.0 : 0.0, 0.0);   // X's column
+        }
+        if (c == jr) xrowj[j][m] = z[jt];                        // row j of X (read only where m <= j)
       }
-      if (c == jr) xrowj[j][m] = z[jt];                        // row j of X (read only where m <= j)
       __syncthreads();
-      const double d0 = colj[j][j].x;
-      const double2 q = colj[j][m], xq = xrowj[j][m];
-      double2 pj[T];
+      if (fw) {
+        const double d0 = colj[j][j].x;
+        const double2 q = colj[j][m], xq = xrowj[j][m];
+        double2 pj[T];
 #pragma unroll
-      for (int t = jt; t < T; ++t) pj[t] = colj[j][C * t + c];
-      const bool okd = d0 > 0.0 && isfinite(d0);
-      badj = (!okd && j < nb && badj == 0) ? k0 + j + 1 : badj;
-      const double dinv = recip(okd ? d0 : 1.0);
-      const bool fac = m > j;
-      const double wx = (fac ? q.x : xq.x) * dinv;
-      const double wy = (fac ? -q.y : xq.y) * dinv;
+        for (int t = jt; t < T; ++t) pj[t] = colj[j][C * t + c];
+        const bool okd = d0 > 0.0 && isfinite(d0);
+        badj = (!okd && j < nb && badj == 0) ? k0 + j + 1 : badj;
+        const double dinv = recip(okd ? d0 : 1.0);
+        const bool fac = m > j;
+        const double wx = (fac ? q.x : xq.x) * dinv;
+        const double wy = (fac ? -q.y : xq.y) * dinv;
 #pragma unroll
-      for (int t = jt; t < T; ++t) {
-        if (t > jt || c > jr) {                                // rows i > j
-          z[t].x -= pj[t].x * wx - pj[t].y * wy;
-          z[t].y -= pj[t].x * wy + pj[t].y * wx;
+        for (int t = jt; t < T; ++t) {
+          if (t > jt || c > jr) {                                // rows i > j
+            z[t].x -= pj[t].x * wx - pj[t].y * wy;
+            z[t].y -= pj[t].x * wy + pj[t].y * wx;
+          }
         }
       }
     };
     static_for(step, std::make_integer_sequence<int, NB>{});
+    if (fw) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) x[C * t + c][m] = C * t + c >= m ? z[t] : make_double2(0.0, 0.0);
+      for (int t = 0; t < T; ++t) x[C * t + c][m] = C * t + c >= m ? z[t] : make_double2(0.0, 0.0);
+    }
     if (tid == 0) bad = badj;
   }
   __syncthreads();
@@ -376,7 +426,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
     rs[tid] = sqrt(d);
   }
   __syncthreads();
-  for (int idx = tid; idx < NB * NB; idx += 256) {
+  for (int idx = tid; idx < NB * NB; idx += PD_THREADS) {
     const int i = idx / NB, j = idx % NB;
     if (j <= i) {
       const double r = rs[j];
@@ -387,39 +437,27 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(const double2 *__restri
   }
   __syncthreads();
   if (blockIdx.x == 0) {
-    for (int idx = tid; idx < NB * NB; idx += 256) {
+    for (int idx = tid; idx < NB * NB; idx += PD_THREADS) {
       const int i = idx / NB, j = idx % NB;
       if (i < nb && j < nb) L[(size_t)(k0 + i) * n + k0 + j] = (j <= i) ? a[i][j] : make_double2(0.0, 0.0);
       linv[idx] = (i < nb && j < nb) ? x[i][j] : make_double2(0.0, 0.0);
     }
     if (tid == 0 && bad != 0 && *pivot == 0) *pivot = bad;
   }
-  // panel below the block, PR rows per workgroup (every workgroup factored the block above for itself):
+  // panel below the block, one entry per thread (every workgroup factored the block above for itself):
   // L[r][k0 + j] = sum_{k <= j} A[r][k0 + k] conj(Linv[j][k]).  Linv is lower triangular with its upper
-  // part stored as zeros, so the k loop runs to NB for every thread: no divergence, and PR / 8
-  // independent accumulators per thread (rows pib + 8t of column pj).
+  // part stored as zeros, so the k loop runs to NB for every thread: no divergence.
   if (r0 >= n) return;
-#pragma unroll
-  for (int t = 0; t < PR * NB / 256; ++t) pa[pib + 8 * t][pj] = pv[t];
+  pa[pib][pj] = pv;
   __syncthreads();
-  double2 acc[PR * NB / 256];
-#pragma unroll
-  for (int t = 0; t < PR * NB / 256; ++t) acc[t] = make_double2(0.0, 0.0);
-#pragma unroll 4
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 8
   for (int k = 0; k < NB; ++k) {
-    const double2 v = x[pj][k];
-#pragma unroll
-    for (int t = 0; t < PR * NB / 256; ++t) {
-      const double2 av = pa[pib + 8 * t][k];
-      acc[t].x += av.x * v.x + av.y * v.y;
-      acc[t].y += av.y * v.x - av.x * v.y;
-    }
+    const double2 v = x[pj][k], av = pa[pib][k];
+    acc.x += av.x * v.x + av.y * v.y;
+    acc.y += av.y * v.x - av.x * v.y;
   }
-#pragma unroll
-  for (int t = 0; t < PR * NB / 256; ++t) {
-    const int r = r0 + pib + 8 * t;
-    if (r < n && pj < nb) L[(size_t)r * n + k0 + pj] = acc[t];
-  }
+  if (r0 + pib < n && pj < nb) L[(size_t)(r0 + pib) * n + k0 + pj] = acc;
 }
 
 __global__ void fill_identity_kernel(double2 *__restrict__ a, int n, double diag) {
@@ -460,7 +498,6 @@ hipError_t launch_fill_int(int *p, int value, hipStream_t s) {
 // The columns of B are independent, so a workgroup carries its SUB_CW columns through the panel's
 // 32-row steps in LDS: X_k = Linv_kk B_k, then B_i -= L_ik X_k for the panel's later row blocks.
 // One launch per panel replaces two small GEMMs per step.
-constexpr int CHOL_PW = 128;   // panel width of the factorisation and the substitution
 constexpr int SUB_CW = 8;      // columns per workgroup
 constexpr int SUB_RS = 256 / SUB_CW;   // row stride of a thread's rows in a 32-row block
 
@@ -580,8 +617,9 @@ hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small
   GW_TRY(launch_fill_int(pivot_dev, 0, s));
   hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, l, n, 0.0);
   GW_TRY(hipGetLastError());
-  // Panels of PW columns: inside a panel each NB-wide step updates only the panel's columns; one
-  // K = PW product then updates everything right of (factorisation) or below (substitution) the panel,
+  // Panels of PW columns: inside a panel each NB-wide step of the factorisation first applies the panel's
+  // earlier columns to its own (left-looking, inside the diagonal-block kernel, so a step is one launch);
+  // one K = PW product then updates everything right of (factorisation) or below (substitution) the panel,
   // so the large trailing matrix is read and written once per panel instead of once per NB step.
   // (A look-ahead that moved each panel's trailing product to a second stream, so that the next panel's
   // chain could start at once, measured slower at N = 4067: the product's workgroups fill the CUs the
@@ -594,17 +632,10 @@ hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small
       const int kb = k0 / NB, nb = min(NB, n - k0), rest = n - k0 - nb;
       double2 *linv = small + (size_t)kb * NB * NB;
       // the diagonal block and, in the same launch, the panel column L[k0+nb:, k0:k0+nb] = A Linv^H
-      hipLaunchKernelGGL(potrf_diag_kernel, dim3(std::max(1, (rest + PR - 1) / PR)), dim3(256), 0, s, a, n, k0, l, linv,
-                         pivot_dev);
+      // (the panel's earlier columns are applied inside it, left-looking)
+      hipLaunchKernelGGL(potrf_diag_kernel, dim3(std::max(1, (rest + PR - 1) / PR)), dim3(PD_THREADS), 0, s, a, n, p0,
+                         k0, l, linv, pivot_dev);
       GW_TRY(hipGetLastError());
-      if (rest > 0) {
-        // the rest of this panel's columns: A[k0+nb:, k0+nb:p1] -= Lp Lp[k0+nb:p1]^H
-        const double2 *lp = l + (size_t)(k0 + nb) * n + k0;
-        const int wcols = p1 - (k0 + nb);
-        if (wcols > 0)
-          GW_TRY(zgemm(rest, wcols, nb, lp, n, 0, lp, n, 1, a + (size_t)(k0 + nb) * n + k0 + nb, n, -1.0, 1.0, 1, 0,
-                       s));
-      }
     }
     // right of the panel: A[p1:, p1:] -= L[p1:, p0:p1] L[p1:, p0:p1]^H (lower tiles)
     const int rest = n - p1;
