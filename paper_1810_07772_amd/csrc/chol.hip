@@ -21,16 +21,33 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int GT = 64;    // output tile
 constexpr int GK = 4;     // complex k per stage (8: 2% slower for the inverse at N = 4067, 16: 18% slower)
 
+// The second product of a combined launch (lower_only == 3): same A, K, alpha, beta and leading
+// dimensions, its own B, C and column count, over a full grid of tiles numbered after the first
+// product's ntile1 lower tiles.
+struct Zg2 {
+  const double2 *B;
+  double2 *C;
+  int transB, N, ntile1;
+};
+
 __global__ __launch_bounds__(256, 4) void zgemm_kernel(int M, int N, int K, const double2 *__restrict__ A, long long lda,
                                                     int transA, const double2 *__restrict__ B, long long ldb,
                                                     int transB, double2 *__restrict__ C, long long ldc, double alpha,
                                                     double beta, int lower_only, int tri_k, int kchunk,
-                                                    long long cz_stride) {
+                                                    long long cz_stride, Zg2 z2) {
   // lower_only == 2: a square product over a one-dimensional grid of its lower tiles only, numbered row
   // by row (t = r (r + 1) / 2 + c), so consecutive workgroups, which the dispatcher deals out to the XCDs
   // in turn, carry equal work and no workgroup is launched for an upper tile
   int row0, col0;
-  if (lower_only == 2) {
+  if (lower_only == 3 && (int)blockIdx.x >= z2.ntile1) {
+    const int t = (int)blockIdx.x - z2.ntile1, nct = (z2.N + GT - 1) / GT;
+    row0 = (t / nct) * GT;
+    col0 = (t % nct) * GT;
+    B = z2.B;
+    C = z2.C;
+    transB = z2.transB;
+    N = z2.N;
+  } else if (lower_only >= 2) {
     const int t = blockIdx.x;
     int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
     while ((r + 1) * (r + 2) / 2 <= t) ++r;
@@ -191,12 +208,24 @@ static hipError_t zgemm(int M, int N, int K, const double2 *A, long long lda, in
   if (lower_only && M == N) {
     const long long nt = (N + GT - 1) / GT;
     hipLaunchKernelGGL(zgemm_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, s, M, N, K, A, lda, transA, B,
-                       ldb, transB, C, ldc, alpha, beta, 2, tri_k, 0, 0LL);
+                       ldb, transB, C, ldc, alpha, beta, 2, tri_k, 0, 0LL, Zg2{});
     return hipGetLastError();
   }
   dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
   hipLaunchKernelGGL(zgemm_kernel, grid, dim3(256), 0, s, M, N, K, A, lda, transA, B, ldb, transB, C, ldc, alpha,
-                     beta, lower_only, tri_k, 0, 0LL);
+                     beta, lower_only, tri_k, 0, 0LL, Zg2{});
+  return hipGetLastError();
+}
+
+// C1 = alpha A B1^H + beta C1 on the lower tiles of the square M x M C1, and C2 = alpha A B2 + beta C2 on
+// all tiles of the M x N2 C2, in one launch (both operands B row-major with leading dimension ldb)
+static hipError_t zgemm_lower_and_full(int M, int N2, int K, const double2 *A, long long lda, const double2 *B1,
+                                       double2 *C1, const double2 *B2, double2 *C2, long long ldb, long long ldc,
+                                       double alpha, double beta, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  const long long nt = (M + GT - 1) / GT, nt1 = nt * (nt + 1) / 2, nt2 = N2 > 0 ? nt * ((N2 + GT - 1) / GT) : 0;
+  hipLaunchKernelGGL(zgemm_kernel, dim3((unsigned)(nt1 + nt2)), dim3(256), 0, s, M, M, K, A, lda, 0, B1, ldb, 1, C1,
+                     ldc, alpha, beta, 3, 0, 0, 0LL, Zg2{B2, C2, 0, N2, (int)nt1});
   return hipGetLastError();
 }
 
@@ -242,7 +271,7 @@ hipError_t launch_zgemm_splitk(int M, int N, int K, const double2 *A, long long 
   dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, kz);
   // each z slice writes every (i, j) of its partial (padded k past kend reads zero), so ws needs no clearing
   hipLaunchKernelGGL(zgemm_kernel, grid, dim3(256), 0, s, M, N, K, A, lda, transA, B, ldb, transB, ws, (long long)N,
-                     1.0, 0.0, 0, 0, kchunk, (long long)M * N);
+                     1.0, 0.0, 0, 0, kchunk, (long long)M * N, Zg2{});
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)(((size_t)M * N + 255) / 256)), dim3(256), 0, s, ws, kz, M,
                      N, C, ldc, alpha, beta);
   return hipGetLastError();
@@ -617,49 +646,44 @@ hipError_t hpd_inverse(double2 *a, int n, double2 *l, double2 *x, double2 *small
   GW_TRY(launch_fill_int(pivot_dev, 0, s));
   hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, l, n, 0.0);
   GW_TRY(hipGetLastError());
-  // Panels of PW columns: inside a panel each NB-wide step of the factorisation first applies the panel's
-  // earlier columns to its own (left-looking, inside the diagonal-block kernel, so a step is one launch);
-  // one K = PW product then updates everything right of (factorisation) or below (substitution) the panel,
-  // so the large trailing matrix is read and written once per panel instead of once per NB step.
+  // the substitution's right-hand side B = I lives in out until X^H X overwrites it
+  hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, out, n, 1.0);
+  GW_TRY(hipGetLastError());
+  hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, x, n, 0.0);
+  GW_TRY(hipGetLastError());
+  // Panels of PW columns, factorisation and substitution interleaved.  Inside a panel each NB-wide step of
+  // the factorisation first applies the panel's earlier columns to its own (left-looking, inside the
+  // diagonal-block kernel, so a step is one launch).  The panel's rows of X = L^-1 need only L's rows of
+  // this panel and B's rows, so they follow at once.  Then one launch of K = PW products updates both
+  // what lies right of the panel in A and below it in B, with the same left operand L[p1:, p0:p1]: the
+  // large trailing matrices are read and written once per panel, and the two products fill the GPU
+  // together where one alone would leave CUs idle (few trailing rows late, few B columns early).
   // (A look-ahead that moved each panel's trailing product to a second stream, so that the next panel's
   // chain could start at once, measured slower at N = 4067: the product's workgroups fill the CUs the
   // chain's small launches wait for.)
   constexpr int PW = CHOL_PW;   // 128, 256 and 512 measured alike; 32 (no panels) 5% slower at N = 4067
-  // 1. factor a = L L^H
   for (int p0 = 0; p0 < n; p0 += PW) {
     const int p1 = min(n, p0 + PW);
+    // 1. factor the panel: L[p0:, p0:p1]
     for (int k0 = p0; k0 < p1; k0 += NB) {
       const int kb = k0 / NB, nb = min(NB, n - k0), rest = n - k0 - nb;
       double2 *linv = small + (size_t)kb * NB * NB;
       // the diagonal block and, in the same launch, the panel column L[k0+nb:, k0:k0+nb] = A Linv^H
-      // (the panel's earlier columns are applied inside it, left-looking)
       hipLaunchKernelGGL(potrf_diag_kernel, dim3(std::max(1, (rest + PR - 1) / PR)), dim3(PD_THREADS), 0, s, a, n, p0,
                          k0, l, linv, pivot_dev);
       GW_TRY(hipGetLastError());
     }
-    // right of the panel: A[p1:, p1:] -= L[p1:, p0:p1] L[p1:, p0:p1]^H (lower tiles)
+    // 2. the panel's rows of X (columns < p1; X is zero beyond), all 32-row steps in one launch
+    hipLaunchKernelGGL(subst_panel_kernel, dim3((p1 + SUB_CW - 1) / SUB_CW), dim3(256), 0, s, out, l, small, x, n, p0,
+                       p1);
+    GW_TRY(hipGetLastError());
+    // 3. A[p1:, p1:] -= Lp Lp^H (lower tiles) and B[p1:, :p1] -= Lp X[p0:p1, :p1], Lp = L[p1:, p0:p1]
     const int rest = n - p1;
     if (rest > 0) {
       const double2 *lp = l + (size_t)p1 * n + p0;
-      GW_TRY(zgemm(rest, rest, p1 - p0, lp, n, 0, lp, n, 1, a + (size_t)p1 * n + p1, n, -1.0, 1.0, 1, 0, s));
+      GW_TRY(zgemm_lower_and_full(rest, p1, p1 - p0, lp, n, lp, a + (size_t)p1 * n + p1, x + (size_t)p0 * n,
+                                  out + (size_t)p1 * n, n, n, -1.0, 1.0, s));
     }
-  }
-  // 2. X = L^-1 by right-looking block substitution on B = I (B reuses a)
-  hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, a, n, 1.0);
-  GW_TRY(hipGetLastError());
-  hipLaunchKernelGGL(fill_identity_kernel, dim3(fill_blocks), dim3(256), 0, s, x, n, 0.0);
-  GW_TRY(hipGetLastError());
-  for (int p0 = 0; p0 < n; p0 += PW) {
-    const int p1 = min(n, p0 + PW);
-    // the panel's rows of X (columns < p1; X is zero beyond), all 32-row steps in one launch
-    hipLaunchKernelGGL(subst_panel_kernel, dim3((p1 + SUB_CW - 1) / SUB_CW), dim3(256), 0, s, a, l, small, x, n, p0,
-                       p1);
-    GW_TRY(hipGetLastError());
-    // below the panel: B[p1:, :p1] -= L[p1:, p0:p1] X[p0:p1, :p1]
-    const int rest = n - p1;
-    if (rest > 0)
-      GW_TRY(zgemm(rest, p1, p1 - p0, l + (size_t)p1 * n + p0, n, 0, x + (size_t)p0 * n, n, 0, a + (size_t)p1 * n, n,
-                   -1.0, 1.0, 0, 0, s));
   }
   // 3. out = X^H X (lower tiles, k from max(row, col) since X is lower triangular), then mirror
   GW_TRY(zgemm(n, n, n, x, n, 1, x, n, 0, out, n, 1.0, 0.0, 1, 1, s));
