@@ -339,40 +339,54 @@ __global__ __launch_bounds__(PD_THREADS) void potrf_diag_kernel(const double2 *_
   // are applied here, A[k0:, k0:k0+nb] -= L[k0:, p0:k0] L[k0:k0+nb, p0:k0]^H, to this workgroup's copy of
   // the diagonal block and to its panel rows, instead of by a separate product after every step.  One
   // panel entry per thread and the block's 528 lower entries over the eight waves.
-  const int kp = k0 - p0;
+  const int kp = k0 - p0;                                   // a multiple of NB
+  static_assert(2 * PR == NB, "rows pib and pib + PR cover the block");
   if (kp > 0) {
-    for (int idx = tid; idx < NB * kp; idx += PD_THREADS) {
-      const int i = idx / kp, k = idx % kp;
-      lb[i][k] = i < nb ? L[(size_t)(k0 + i) * n + p0 + k] : make_double2(0.0, 0.0);
-    }
-    for (int idx = tid; idx < PR * kp; idx += PD_THREADS) {
-      const int i = idx / kp, k = idx % kp;
-      lr[i][k] = r0 + i < n ? L[(size_t)(r0 + i) * n + p0 + k] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < (CHOL_PW - NB) / NB; ++q) {
+      if (NB * q < kp) {                                     // column k = pj + NB q; rows pib and pib + PR
+        const int k = pj + NB * q;
+        lb[pib][k] = pib < nb ? L[(size_t)(k0 + pib) * n + p0 + k] : make_double2(0.0, 0.0);
+        lb[pib + PR][k] = pib + PR < nb ? L[(size_t)(k0 + pib + PR) * n + p0 + k] : make_double2(0.0, 0.0);
+        lr[pib][k] = r0 + pib < n ? L[(size_t)(r0 + pib) * n + p0 + k] : make_double2(0.0, 0.0);
+      }
     }
     __syncthreads();
-    double2 acc = make_double2(0.0, 0.0);
+    // each thread: its panel entry and lower entry e = tid of the block (numbered row by row, diagonal
+    // included) in one loop; the block's last NB (NB + 1) / 2 - PD_THREADS entries in a second one
+    auto lower_entry = [](int e, int &i, int &j) {
+      i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+      while ((i + 1) * (i + 2) / 2 <= e) ++i;
+      while (i * (i + 1) / 2 > e) --i;
+      j = e - i * (i + 1) / 2;
+    };
+    int bi, bj;
+    lower_entry(tid, bi, bj);
+    double2 acc = make_double2(0.0, 0.0), ad = make_double2(0.0, 0.0);
 #pragma unroll 4
     for (int k = 0; k < kp; ++k) {
-      const double2 u = lr[pib][k], w = lb[pj][k];
+      const double2 u = lr[pib][k], w = lb[pj][k], bu = lb[bi][k], bw = lb[bj][k];
       acc.x += u.x * w.x + u.y * w.y;
       acc.y += u.y * w.x - u.x * w.y;
+      ad.x += bu.x * bw.x + bu.y * bw.y;
+      ad.y += bu.y * bw.x - bu.x * bw.y;
     }
     pv.x -= acc.x;
     pv.y -= acc.y;
-    for (int e = tid; e < NB * (NB + 1) / 2; e += PD_THREADS) {   // lower entries, numbered row by row
-      int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-      while ((i + 1) * (i + 2) / 2 <= e) ++i;
-      while (i * (i + 1) / 2 > e) --i;
-      const int j = e - i * (i + 1) / 2;
-      double2 ad = make_double2(0.0, 0.0);
+    a[bi][bj].x -= ad.x;
+    a[bi][bj].y -= ad.y;
+    constexpr int NLOW = NB * (NB + 1) / 2;
+    if (tid < NLOW - PD_THREADS) {
+      lower_entry(tid + PD_THREADS, bi, bj);
+      ad = make_double2(0.0, 0.0);
 #pragma unroll 4
       for (int k = 0; k < kp; ++k) {
-        const double2 u = lb[i][k], w = lb[j][k];
-        ad.x += u.x * w.x + u.y * w.y;
-        ad.y += u.y * w.x - u.x * w.y;
+        const double2 bu = lb[bi][k], bw = lb[bj][k];
+        ad.x += bu.x * bw.x + bu.y * bw.y;
+        ad.y += bu.y * bw.x - bu.x * bw.y;
       }
-      a[i][j].x -= ad.x;
-      a[i][j].y -= ad.y;
+      a[bi][bj].x -= ad.x;
+      a[bi][bj].y -= ad.y;
     }
   }
   // Unblocked right-looking Cholesky on the lower triangle, with unscaled columns: step j subtracts
