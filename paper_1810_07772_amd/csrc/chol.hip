@@ -1,5 +1,6 @@
 // FP64 inverse of a Hermitian positive definite matrix (eps of Sec. 5.1) by Cholesky:
-//   eps = L L^H  (blocked, right-looking),  X = L^-1 (blocked forward substitution on I),
+//   eps = L L^H  (blocked: right-looking between panels of 128 columns, left-looking inside one),
+//   X = L^-1 (blocked forward substitution on I, panel by panel behind the factorisation),
 //   eps^-1 = X^H X.
 // The paper inverts eps with a Newton iteration built on matrix products because that
 // parallelises across distributed memory; on one GPU the factorisation costs about a
@@ -284,9 +285,10 @@ hipError_t launch_zgemm(int M, int N, int K, const double2 *A, long long lda, in
 }
 
 // ---- diagonal block L_kk = chol(A_kk), Linv_kk = L_kk^-1, and the panel column below it -------------
-// Every workgroup factors and inverts the 32 x 32 block in LDS (cheap, and it saves a dependent launch
-// per step); workgroup 0 stores L_kk, Linv_kk and the pivot flag, and workgroup g forms PR rows of the
-// panel L[k0+nb+PR g : +PR, k0 : k0+nb] = A Linv_kk^H.  With PR = 16 the panel product of a 4067-row
+// Every workgroup first applies the panel's earlier columns to the block and to its panel rows, then
+// factors and inverts the 32 x 32 block in LDS (cheap, and it saves a dependent launch per step);
+// workgroup 0 stores L_kk, Linv_kk and the pivot flag, and workgroup g forms PR rows of the panel
+// L[k0+nb+PR g : +PR, k0 : k0+nb] = A Linv_kk^H.  With PR = 16 the panel product of a 4067-row
 // matrix spreads over about 250 CUs (64 rows per workgroup left three quarters of the CUs idle).
 constexpr int NB = 32;
 constexpr int PR = 16;    // panel rows per workgroup of the diagonal-block kernel
