@@ -315,8 +315,10 @@ __global__ __launch_bounds__(PD_THREADS) void potrf_diag_kernel(const double2 *_
                                                                 int k0, double2 *__restrict__ L,
                                                                 double2 *__restrict__ linv, int *__restrict__ pivot) {
   __shared__ double2 a[NB][NB + 1];
-  __shared__ double2 lb[NB][CHOL_PW - NB + 1];   // L[k0 + i][p0 + k]: the block's rows, earlier panel columns
-  __shared__ double2 lr[PR][CHOL_PW - NB + 1];   // the same columns of this workgroup's panel rows
+  // L[k0 + i][p0 + k] (the block's rows, the panel's earlier columns) and the same columns of this
+  // workgroup's panel rows, planar: [k][re, im][row], the operand layout of the FP64 MFMA
+  __shared__ double lbp[CHOL_PW - NB][2][NB + 1];
+  __shared__ double lrp[CHOL_PW - NB][2][PR + 1];
   __shared__ double2 x[NB][NB + 1];
   __shared__ double2 pa[PR][NB + 1];
   __shared__ int bad;
@@ -337,10 +339,13 @@ __global__ __launch_bounds__(PD_THREADS) void potrf_diag_kernel(const double2 *_
     a[i][j] = v;
     x[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
+  pa[pib][pj] = pv;
   // Left-looking inside the panel: the kp = k0 - p0 columns of this panel factored by the earlier steps
   // are applied here, A[k0:, k0:k0+nb] -= L[k0:, p0:k0] L[k0:k0+nb, p0:k0]^H, to this workgroup's copy of
-  // the diagonal block and to its panel rows, instead of by a separate product after every step.  One
-  // panel entry per thread and the block's 528 lower entries over the eight waves.
+  // the diagonal block and to its panel rows, instead of by a separate product after every step.  Five
+  // waves each form one 16 x 16 tile on the FP64 MFMA, with k' = (k, re/im) as in zgemm_kernel:
+  // Re C += [Re A, Im A] . [Re B; Im B] and Im C += [Re A, Im A] . [-Im B; Re B] for C = A B^H.  Waves 0
+  // and 1 take the panel rows' two column halves, waves 2 to 4 the block's lower tiles (0,0), (1,0), (1,1).
   const int kp = k0 - p0;                                   // a multiple of NB
   static_assert(2 * PR == NB, "rows pib and pib + PR cover the block");
   if (kp > 0) {
@@ -348,47 +353,47 @@ __global__ __launch_bounds__(PD_THREADS) void potrf_diag_kernel(const double2 *_
     for (int q = 0; q < (CHOL_PW - NB) / NB; ++q) {
       if (NB * q < kp) {                                     // column k = pj + NB q; rows pib and pib + PR
         const int k = pj + NB * q;
-        lb[pib][k] = pib < nb ? L[(size_t)(k0 + pib) * n + p0 + k] : make_double2(0.0, 0.0);
-        lb[pib + PR][k] = pib + PR < nb ? L[(size_t)(k0 + pib + PR) * n + p0 + k] : make_double2(0.0, 0.0);
-        lr[pib][k] = r0 + pib < n ? L[(size_t)(r0 + pib) * n + p0 + k] : make_double2(0.0, 0.0);
+        const double2 u = pib < nb ? L[(size_t)(k0 + pib) * n + p0 + k] : make_double2(0.0, 0.0);
+        const double2 w = pib + PR < nb ? L[(size_t)(k0 + pib + PR) * n + p0 + k] : make_double2(0.0, 0.0);
+        const double2 v = r0 + pib < n ? L[(size_t)(r0 + pib) * n + p0 + k] : make_double2(0.0, 0.0);
+        lbp[k][0][pib] = u.x;
+        lbp[k][1][pib] = u.y;
+        lbp[k][0][pib + PR] = w.x;
+        lbp[k][1][pib + PR] = w.y;
+        lrp[k][0][pib] = v.x;
+        lrp[k][1][pib] = v.y;
       }
     }
     __syncthreads();
-    // each thread: its panel entry and lower entry e = tid of the block (numbered row by row, diagonal
-    // included) in one loop; the block's last NB (NB + 1) / 2 - PD_THREADS entries in a second one
-    auto lower_entry = [](int e, int &i, int &j) {
-      i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-      while ((i + 1) * (i + 2) / 2 <= e) ++i;
-      while (i * (i + 1) / 2 > e) --i;
-      j = e - i * (i + 1) / 2;
-    };
-    int bi, bj;
-    lower_entry(tid, bi, bj);
-    double2 acc = make_double2(0.0, 0.0), ad = make_double2(0.0, 0.0);
-#pragma unroll 4
-    for (int k = 0; k < kp; ++k) {
-      const double2 u = lr[pib][k], w = lb[pj][k], bu = lb[bi][k], bw = lb[bj][k];
-      acc.x += u.x * w.x + u.y * w.y;
-      acc.y += u.y * w.x - u.x * w.y;
-      ad.x += bu.x * bw.x + bu.y * bw.y;
-      ad.y += bu.y * bw.x - bu.x * bw.y;
-    }
-    pv.x -= acc.x;
-    pv.y -= acc.y;
-    a[bi][bj].x -= ad.x;
-    a[bi][bj].y -= ad.y;
-    constexpr int NLOW = NB * (NB + 1) / 2;
-    if (tid < NLOW - PD_THREADS) {
-      lower_entry(tid + PD_THREADS, bi, bj);
-      ad = make_double2(0.0, 0.0);
-#pragma unroll 4
-      for (int k = 0; k < kp; ++k) {
-        const double2 bu = lb[bi][k], bw = lb[bj][k];
-        ad.x += bu.x * bw.x + bu.y * bw.y;
-        ad.y += bu.y * bw.x - bu.x * bw.y;
+    const int wave = tid >> 6, lane = tid & 63, kl = lane >> 4, li = lane & 15;
+    if (wave < 5) {                                          // wave-uniform
+      const bool rows = wave < 2;
+      const int ra = rows ? 0 : (wave == 2 ? 0 : 16);        // first row of the tile (panel rows or block)
+      const int cb = rows ? 16 * wave : (wave == 4 ? 16 : 0);  // first column (block row of B)
+      f64x4 accR = {0.0, 0.0, 0.0, 0.0}, accI = {0.0, 0.0, 0.0, 0.0};
+      const int comp = kl & 1;
+      const unsigned long long flip = comp ? 0ull : 0x8000000000000000ull;   // Y = [-Im B; Re B]
+      for (int s2 = 0; s2 < kp; s2 += 2) {
+        const int kk = s2 + (kl >> 1);
+        const double av = rows ? lrp[kk][comp][li] : lbp[kk][comp][ra + li];
+        const double xv = lbp[kk][comp][cb + li];
+        const double ys = lbp[kk][comp ^ 1][cb + li];
+        const double yv = __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, ys) ^ flip);
+        accR = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xv, accR, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f64_16x16x4f64(av, yv, accI, 0, 0, 0);
       }
-      a[bi][bj].x -= ad.x;
-      a[bi][bj].y -= ad.y;
+      // lane holds tile entry (4 e + kl, li) in register e
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = 4 * e + kl;
+        if (rows) {
+          pa[i][cb + li].x -= accR[e];
+          pa[i][cb + li].y -= accI[e];
+        } else if (ra + i >= cb + li) {                      // lower entries of the block only
+          a[ra + i][cb + li].x -= accR[e];
+          a[ra + i][cb + li].y -= accI[e];
+        }
+      }
     }
   }
   // Unblocked right-looking Cholesky on the lower triangle, with unscaled columns: step j subtracts
@@ -493,8 +498,6 @@ __global__ __launch_bounds__(PD_THREADS) void potrf_diag_kernel(const double2 *_
   // L[r][k0 + j] = sum_{k <= j} A[r][k0 + k] conj(Linv[j][k]).  Linv is lower triangular with its upper
   // part stored as zeros, so the k loop runs to NB for every thread: no divergence.
   if (r0 >= n) return;
-  pa[pib][pj] = pv;
-  __syncthreads();
   double2 acc = make_double2(0.0, 0.0);
 #pragma unroll 8
   for (int k = 0; k < NB; ++k) {
