@@ -207,7 +207,7 @@ def test_epsilon_build(gw):
     assert got[0, 0] == 1.7
 
 
-@pytest.mark.parametrize("n", [1, 31, 32, 100, 257])
+@pytest.mark.parametrize("n", [1, 31, 32, 100, 257, 450])
 def test_hpd_inverse(gw, n):
     rng = np.random.default_rng(n)
     x = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
@@ -227,6 +227,21 @@ def test_hpd_inverse_not_pd(gw):
     with pytest.raises(gw.GwError) as ei:
         gw.hpd_inverse(dev(a))
     assert ei.value.status == 4 and "pivot 41" in str(ei.value)
+
+
+def test_hpd_inverse_not_pd_in_a_later_panel(gw):
+    # A = Lu D Lu^H with a dense unit lower triangular Lu: the factorisation's pivots are D's entries, so the
+    # first non-positive one is pivot 201 (the third 32-wide step of the second 128-column panel, where the
+    # panel's earlier columns are applied before the pivot is seen)
+    n = 300
+    rng = np.random.default_rng(3)
+    lu = np.eye(n) + np.tril(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)), -1) * (0.3 / np.sqrt(n))
+    d = np.ones(n)
+    d[200] = -0.5
+    a = (lu * d) @ lu.conj().T
+    with pytest.raises(gw.GwError) as ei:
+        gw.hpd_inverse(dev(a))
+    assert ei.value.status == 4 and "pivot 201" in str(ei.value)
 
 
 @pytest.mark.parametrize("q,head", [((0, 0, 0), 1.0), ((0.0, 0.0, 0.001), 1.0), ((0.2, 0.1, 0.05), 1.0)])
