@@ -1095,7 +1095,10 @@ __global__ __launch_bounds__(3 * NTHR, 1) void herk_split_wide_planar_kernel(
     return;
   }
 
-  // ---- consumers: quadrant rows I0 + 64 wr, columns J0 + 64 wc
+  // ---- consumers: quadrant rows I0 + 64 wr, columns J0 + 64 wc.  They issue at the highest wave priority,
+  // so that an MFMA ready beside a producer's VALU instruction goes first: 0.2% shorter launches on one
+  // machine, against 2.8% longer with the producers preferred instead.
+  __builtin_amdgcn_s_setprio(3);
   const int wr = wave >> 2, wc = wave & 3;
   const bool active = (wc >> 1) < ncb;                     // wave-uniform: this quadrant is on or below the diagonal
   const int kq = lane >> 5, idx = lane & 31;
